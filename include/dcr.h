@@ -1,0 +1,133 @@
+/*
+ * dcr.h -- C ABI of libdcr: multinomial resampling on AMD Instinct MI355X
+ * (gfx950) by the divide-and-conquer inverse-CMF map of A. A. Popov,
+ * "A divide and conquer strategy for multinomial particle filter resampling".
+ *
+ * The problem (Sec. I, Eqs. 1-3): given M non-negative weights w_j, draw N
+ * indices r_i = P^{-1}(u_i), where P^{-1}(u) is the first bin j whose
+ * normalised cumulative weight W_j = (w_0 + ... + w_j) / (w_0 + ... + w_{M-1})
+ * is >= u, and u_0 <= ... <= u_{N-1} are sorted uniforms (Sec. II, Alg. 1).
+ * Indices are 0-based here (the paper's index i is i-1 here).
+ *
+ * Conventions shared by every entry point
+ *   - Memory: every array argument is a caller-owned DEVICE pointer (for
+ *     example a torch tensor's data_ptr()).  The library never allocates or
+ *     frees device memory; scratch space is the caller's workspace `ws` of
+ *     `ws_bytes` bytes, sized by dcr_workspace_bytes() and 256-byte aligned.
+ *   - Streams: calls enqueue kernels on `stream` and return without
+ *     synchronising; results are valid once the stream has reached them.
+ *     Calls on different streams must not share a workspace.
+ *   - Errors: problems visible on the host (NULL pointers with a non-zero
+ *     size, sizes out of range, an unknown precision, a small workspace) return
+ *     an error before anything is enqueued.  Problems in the data (a weight
+ *     that is negative, NaN or infinite, or a zero / infinite total) are found
+ *     on the device: then `*dev_status` (if not NULL) receives
+ *     DCR_ERR_BAD_WEIGHTS, every r_i is set to -1 and W is not meaningful;
+ *     otherwise `*dev_status` receives DCR_OK.  A failed HIP launch returns
+ *     DCR_ERR_HIP.
+ *   - Sizes: 1 <= M <= 2^31 - 1 and 0 <= N <= 2^31 - 2; N = 0 draws nothing.
+ *     N > M is allowed.
+ *   - Randomness: draw i of (seed, stream_id) comes from Philox4x32-10
+ *     (Salmon et al., SC'11), so every call is reproducible and streams are
+ *     independent; a particle filter may use its time step as stream_id.
+ */
+#ifndef DCR_H
+#define DCR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum dcr_status {
+    DCR_OK = 0,
+    DCR_ERR_INVALID_ARGUMENT = 1,
+    DCR_ERR_UNSUPPORTED = 2,
+    DCR_ERR_WORKSPACE_TOO_SMALL = 3,
+    DCR_ERR_CAPACITY_EXCEEDED = 4,
+    DCR_ERR_HIP = 5,
+    DCR_ERR_BAD_WEIGHTS = 6,
+    DCR_ERR_INTERNAL = 7
+} dcr_status;
+
+/* Precision form.
+ *   DCR_FP64:      w is binary64; z = -log v in binary64.
+ *   DCR_FP32_COMP: w is binary32 (promoted exactly, sums carried in binary64);
+ *                  z = -logf(fl32(v)) in binary32, sums carried in binary64.
+ * In both forms W and u are returned as binary64. */
+typedef enum dcr_precision {
+    DCR_FP64 = 0,
+    DCR_FP32_COMP = 1
+} dcr_precision;
+
+/* Human-readable name of a status code (static string, never NULL). */
+const char* dcr_status_string(dcr_status s);
+
+/* Workspace bytes needed by any single-distribution call below with sizes
+ * (M, N) and precision p.  Host only; enqueues nothing.
+ * Errors: DCR_ERR_INVALID_ARGUMENT for sizes out of range or bytes == NULL,
+ * DCR_ERR_UNSUPPORTED for an unknown precision. */
+dcr_status dcr_workspace_bytes(int64_t M, int64_t N, dcr_precision p, size_t* bytes);
+
+/* Stage 1 -- Sec. I, Eq. 3: normalised cumulative weights.
+ *   w        [M] binary64 (DCR_FP64) or binary32 (DCR_FP32_COMP), contiguous.
+ *   W        [M] binary64 out: non-decreasing, W[M-1] == 1 exactly.
+ *   total    [1] binary64 out (may be NULL): the sum the weights are divided by.
+ *   dev_status [1] int32 out (may be NULL): DCR_OK or DCR_ERR_BAD_WEIGHTS.
+ * The summation order is fixed (blocked, sequential within every level), so
+ * repeated calls return identical bits. */
+dcr_status dcr_cumulative_weights(const void* w, int64_t M, dcr_precision p, double* W,
+                                  double* total, int32_t* dev_status, void* ws,
+                                  size_t ws_bytes, hipStream_t stream);
+
+/* Stage 2 -- Sec. II, Alg. 1: N sorted uniforms by exponential spacings.
+ *   z_i = -log v_i for i = 0..N, Z_i = z_0 + ... + z_i, u_i = Z_i / Z_N.
+ *   u        [N] binary64 out: non-decreasing, in (0, 1]. */
+dcr_status dcr_sorted_uniforms(int64_t N, uint64_t seed, uint64_t stream_id, dcr_precision p,
+                               double* u, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Stage 3 -- Sec. III, Alg. 5 (with Alg. 2 and Alg. 4 as its base cases): the
+ * inverse CMF of sorted uniforms.
+ *   W        [M] binary64, non-decreasing (precondition, not checked).
+ *   u        [N] binary64, non-decreasing (precondition, not checked).
+ *   r        [N] int32 out: r_i = #{ j in [0, M-2] : W_j < u_i }, i.e. the first
+ *            j with W_j >= u_i, clamped to M-1.  The result is exact: it does
+ *            not depend on how the search is organised. */
+dcr_status dcr_inverse_cmf(const double* W, int64_t M, const double* u, int64_t N, int32_t* r,
+                           void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* End to end -- Sec. III, Alg. 5 "DaCSampler": stage 1, stage 2 and stage 3.
+ *   w, M, p      as in dcr_cumulative_weights.
+ *   N, seed, stream_id  as in dcr_sorted_uniforms.
+ *   r        [N] int32 out, non-decreasing.
+ *   W_opt    [M] binary64 out or NULL (then W is never written to memory).
+ *   u_opt    [N] binary64 out or NULL.
+ *   dev_status [1] int32 out or NULL.
+ * r equals dcr_inverse_cmf applied to the W of dcr_cumulative_weights and the u
+ * of dcr_sorted_uniforms with the same arguments, bit for bit. */
+dcr_status dcr_resample(const void* w, int64_t M, int64_t N, uint64_t seed, uint64_t stream_id,
+                        dcr_precision p, int32_t* r, double* W_opt, double* u_opt,
+                        int32_t* dev_status, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Kernel timing for measurement (not part of the sampling contract).
+ * dcr_profile_begin(cap) creates HIP events for up to `cap` kernel launches
+ * and makes every later call record an event pair around each kernel it
+ * enqueues.  dcr_profile_end() synchronises on the last event, stops
+ * recording and, for each kernel kind k (see dcr_profile_kind_name), stores
+ * the launch count in counts[k] and the summed milliseconds in ms[k]
+ * (arrays of n_kinds entries, host memory).  Kinds beyond n_kinds are dropped.
+ * Not thread safe; meant for one measuring thread. */
+dcr_status dcr_profile_begin(int32_t cap);
+dcr_status dcr_profile_end(int32_t n_kinds, int64_t* counts, double* ms);
+int32_t dcr_profile_kind_count(void);
+const char* dcr_profile_kind_name(int32_t kind);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DCR_H */

@@ -1,0 +1,25 @@
+"""paper_2604_01356_amd -- divide-and-conquer multinomial resampling on MI355X.
+
+A thin Python binding over libdcr.so (include/dcr.h).  The functions carry
+the C names and only marshal arguments: torch tensors supply device memory and
+the current HIP stream; every step of the computation runs in the library's
+HIP kernels.  Importing this package does not load the library; the first call
+does, and fails loudly if the library has not been built.
+"""
+from ._binding import (  # noqa: F401
+    DCR_FP32_COMP,
+    DCR_FP64,
+    DcrError,
+    dcr_cumulative_weights,
+    dcr_inverse_cmf,
+    dcr_profile_begin,
+    dcr_profile_end,
+    dcr_resample,
+    dcr_sorted_uniforms,
+    dcr_status_string,
+    dcr_workspace_bytes,
+    library,
+    library_path,
+    precision_of,
+    STATUS,
+)

@@ -1,0 +1,219 @@
+"""ctypes marshalling for libdcr.so (declarations in include/dcr.h).
+
+Device arrays are torch tensors on a HIP device; their data pointers and the
+current stream of their device are handed to the C ABI unchanged.  Nothing
+here computes any part of the resampling.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libdcr.so")
+_lib = None
+
+DCR_FP64 = 0
+DCR_FP32_COMP = 1
+
+STATUS = {
+    0: "DCR_OK",
+    1: "DCR_ERR_INVALID_ARGUMENT",
+    2: "DCR_ERR_UNSUPPORTED",
+    3: "DCR_ERR_WORKSPACE_TOO_SMALL",
+    4: "DCR_ERR_CAPACITY_EXCEEDED",
+    5: "DCR_ERR_HIP",
+    6: "DCR_ERR_BAD_WEIGHTS",
+    7: "DCR_ERR_INTERNAL",
+}
+
+
+class DcrError(RuntimeError):
+    def __init__(self, where: str, code: int):
+        self.code = code
+        super().__init__(f"{where}: {STATUS.get(code, code)} ({_status_text(code)})")
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def library():
+    """Load libdcr.so; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(
+            f"{_LIB_PATH} is not built; run `python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = ctypes.CDLL(_LIB_PATH)
+    P, i64, u64, i32, sz = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_int32,
+                            ctypes.c_size_t)
+    lib.dcr_status_string.argtypes = [ctypes.c_int]
+    lib.dcr_status_string.restype = ctypes.c_char_p
+    lib.dcr_workspace_bytes.argtypes = [i64, i64, ctypes.c_int, ctypes.POINTER(sz)]
+    lib.dcr_workspace_bytes.restype = ctypes.c_int
+    lib.dcr_cumulative_weights.argtypes = [P, i64, ctypes.c_int, P, P, P, P, sz, P]
+    lib.dcr_cumulative_weights.restype = ctypes.c_int
+    lib.dcr_sorted_uniforms.argtypes = [i64, u64, u64, ctypes.c_int, P, P, sz, P]
+    lib.dcr_sorted_uniforms.restype = ctypes.c_int
+    lib.dcr_inverse_cmf.argtypes = [P, i64, P, i64, P, P, sz, P]
+    lib.dcr_inverse_cmf.restype = ctypes.c_int
+    lib.dcr_resample.argtypes = [P, i64, i64, u64, u64, ctypes.c_int, P, P, P, P, P, sz, P]
+    lib.dcr_resample.restype = ctypes.c_int
+    lib.dcr_profile_begin.argtypes = [i32]
+    lib.dcr_profile_begin.restype = ctypes.c_int
+    lib.dcr_profile_end.argtypes = [i32, P, P]
+    lib.dcr_profile_end.restype = ctypes.c_int
+    lib.dcr_profile_kind_count.argtypes = []
+    lib.dcr_profile_kind_count.restype = i32
+    lib.dcr_profile_kind_name.argtypes = [i32]
+    lib.dcr_profile_kind_name.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _status_text(code: int) -> str:
+    try:
+        return library().dcr_status_string(int(code)).decode()
+    except Exception:  # pragma: no cover - library missing while formatting an error
+        return ""
+
+
+def _check(where: str, code: int):
+    if code != 0:
+        raise DcrError(where, code)
+
+
+def dcr_status_string(code: int) -> str:
+    return library().dcr_status_string(int(code)).decode()
+
+
+def precision_of(w) -> int:
+    import torch
+    if w.dtype == torch.float64:
+        return DCR_FP64
+    if w.dtype == torch.float32:
+        return DCR_FP32_COMP
+    raise TypeError(f"weights must be float64 or float32, got {w.dtype}")
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(device):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _dev_tensor(t, name, dtype=None, numel=None):
+    if t is None:
+        return
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name} holds {t.numel()} elements, needs {numel}")
+
+
+def dcr_workspace_bytes(M: int, N: int, precision: int = DCR_FP64) -> int:
+    out = ctypes.c_size_t(0)
+    _check("dcr_workspace_bytes",
+           library().dcr_workspace_bytes(int(M), int(N), int(precision), ctypes.byref(out)))
+    return int(out.value)
+
+
+def _workspace(ws, M, N, precision, device):
+    import torch
+    need = dcr_workspace_bytes(M, N, precision)
+    if ws is None:
+        return torch.empty(max(need, 256), dtype=torch.uint8, device=device)
+    _dev_tensor(ws, "ws")
+    return ws
+
+
+def dcr_cumulative_weights(w, W=None, total=None, dev_status=None, ws=None):
+    """Stage 1: normalised cumulative weights of w (float64 or float32)."""
+    import torch
+    _dev_tensor(w, "w")
+    M = w.numel()
+    p = precision_of(w)
+    if W is None:
+        W = torch.empty(M, dtype=torch.float64, device=w.device)
+    _dev_tensor(W, "W", torch.float64, M)
+    _dev_tensor(total, "total", torch.float64, 1)
+    _dev_tensor(dev_status, "dev_status", torch.int32, 1)
+    ws = _workspace(ws, M, 0, p, w.device)
+    _check("dcr_cumulative_weights", library().dcr_cumulative_weights(
+        _ptr(w), M, p, _ptr(W), _ptr(total), _ptr(dev_status), _ptr(ws), ws.numel(),
+        _stream(w.device)))
+    return W
+
+
+def dcr_sorted_uniforms(N: int, seed: int, stream_id: int = 0, precision: int = DCR_FP64,
+                        u=None, ws=None, device="cuda"):
+    """Stage 2: N sorted uniforms of (seed, stream_id)."""
+    import torch
+    if u is None:
+        u = torch.empty(max(int(N), 1), dtype=torch.float64, device=device)
+    _dev_tensor(u, "u", torch.float64, int(N))
+    ws = _workspace(ws, 1, N, precision, u.device)
+    _check("dcr_sorted_uniforms", library().dcr_sorted_uniforms(
+        int(N), int(seed), int(stream_id), int(precision), _ptr(u), _ptr(ws), ws.numel(),
+        _stream(u.device)))
+    return u[: int(N)]
+
+
+def dcr_inverse_cmf(W, u, r=None):
+    """Stage 3: r_i = first j with W_j >= u_i (clamped to M-1)."""
+    import torch
+    _dev_tensor(W, "W", torch.float64)
+    _dev_tensor(u, "u", torch.float64)
+    N = u.numel()
+    if r is None:
+        r = torch.empty(max(N, 1), dtype=torch.int32, device=u.device)
+    _dev_tensor(r, "r", torch.int32, N)
+    _check("dcr_inverse_cmf", library().dcr_inverse_cmf(
+        _ptr(W), W.numel(), _ptr(u), N, _ptr(r), None, 0, _stream(u.device)))
+    return r[:N]
+
+
+def dcr_resample(w, N: int, seed: int, stream_id: int = 0, r=None, W_out=None, u_out=None,
+                 dev_status=None, ws=None):
+    """End to end: N indices drawn from the weights w (float64 or float32)."""
+    import torch
+    _dev_tensor(w, "w")
+    M = w.numel()
+    p = precision_of(w)
+    N = int(N)
+    if r is None:
+        r = torch.empty(max(N, 1), dtype=torch.int32, device=w.device)
+    _dev_tensor(r, "r", torch.int32, N)
+    _dev_tensor(W_out, "W_out", torch.float64, M)
+    _dev_tensor(u_out, "u_out", torch.float64, N)
+    _dev_tensor(dev_status, "dev_status", torch.int32, 1)
+    ws = _workspace(ws, M, N, p, w.device)
+    _check("dcr_resample", library().dcr_resample(
+        _ptr(w), M, N, int(seed), int(stream_id), p, _ptr(r), _ptr(W_out), _ptr(u_out),
+        _ptr(dev_status), _ptr(ws), ws.numel(), _stream(w.device)))
+    return r[:N]
+
+
+def dcr_profile_begin(cap: int):
+    _check("dcr_profile_begin", library().dcr_profile_begin(int(cap)))
+
+
+def dcr_profile_end() -> dict:
+    """Stop kernel timing; returns {kind name: (launches, total ms)}."""
+    lib = library()
+    n = lib.dcr_profile_kind_count()
+    counts = (ctypes.c_int64 * n)()
+    ms = (ctypes.c_double * n)()
+    _check("dcr_profile_end", lib.dcr_profile_end(n, ctypes.addressof(counts),
+                                                  ctypes.addressof(ms)))
+    return {lib.dcr_profile_kind_name(k).decode(): (int(counts[k]), float(ms[k]))
+            for k in range(n)}

@@ -1,0 +1,306 @@
+// dcr_api.hip -- host side of the libdcr C ABI (declared in include/dcr.h):
+// argument validation, workspace layout and kernel enqueueing.  Nothing here
+// allocates device memory; scratch space is the caller's workspace.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "dcr.h"
+#include "dcr_internal.hpp"
+
+namespace {
+
+using dcr::SharedArgs;
+using dcr::WArgs;
+using dcr::ZArgs;
+
+constexpr int64_t kMaxM = 2147483647LL;   // r is int32
+constexpr int64_t kMaxN = 2147483646LL;   // N + 1 draws must stay below 2^31
+constexpr int64_t kWBlock = 32768;
+constexpr int64_t kWSubPerBlock = 128;
+constexpr int64_t kZBlock = 4096;
+
+size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+// Workspace layout: [header][weight side][spacing side][uniforms]
+struct Layout {
+    int64_t nwb = 0, nzb = 0;
+    size_t status = 0, totals = 0;
+    size_t w_tot = 0, w_bad = 0, w_beta = 0, w_sub = 0;
+    size_t z_tot = 0, z_beta = 0, z_buf = 0;
+    size_t u_buf = 0;
+    size_t bytes = 0;
+};
+
+Layout make_layout(int64_t M, int64_t N, bool want_u_buf) {
+    Layout L;
+    size_t off = 0;
+    L.status = off;
+    off += 256;
+    L.totals = off;
+    off += 256;
+    if (M > 0) {
+        L.nwb = (M + kWBlock - 1) / kWBlock;
+        L.w_tot = off;
+        off = align256(off + sizeof(double) * L.nwb);
+        L.w_bad = off;
+        off = align256(off + sizeof(int32_t) * L.nwb);
+        L.w_beta = off;
+        off = align256(off + sizeof(double) * L.nwb);
+        L.w_sub = off;
+        off = align256(off + sizeof(double) * L.nwb * kWSubPerBlock);
+    }
+    if (N > 0) {
+        L.nzb = (N + 1 + kZBlock - 1) / kZBlock;
+        L.z_tot = off;
+        off = align256(off + sizeof(double) * L.nzb);
+        L.z_beta = off;
+        off = align256(off + sizeof(double) * L.nzb);
+        L.z_buf = off;
+        off = align256(off + sizeof(double) * L.nzb * kZBlock);
+        if (want_u_buf) {
+            L.u_buf = off;
+            off = align256(off + sizeof(double) * N);
+        }
+    }
+    L.bytes = off;
+    return L;
+}
+
+template <typename T>
+T* at(void* ws, size_t off) {
+    return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+bool valid_prec(dcr_precision p) { return p == DCR_FP64 || p == DCR_FP32_COMP; }
+int prec_code(dcr_precision p) { return p == DCR_FP32_COMP ? dcr::kPrecFP32 : dcr::kPrecFP64; }
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+WArgs w_args(const Layout& L, void* ws, int64_t M) {
+    WArgs a{};
+    a.M = M;
+    a.nb = L.nwb;
+    a.blk_tot = at<double>(ws, L.w_tot);
+    a.blk_bad = at<int32_t>(ws, L.w_bad);
+    a.beta = at<double>(ws, L.w_beta);
+    a.sub_end = at<double>(ws, L.w_sub);
+    return a;
+}
+
+ZArgs z_args(const Layout& L, void* ws, int64_t N, uint64_t seed, uint64_t stream) {
+    ZArgs a{};
+    a.N = N;
+    a.nb = L.nzb;
+    a.seed = seed;
+    a.stream = stream;
+    a.zbuf = at<double>(ws, L.z_buf);
+    a.blk_tot = at<double>(ws, L.z_tot);
+    a.beta = at<double>(ws, L.z_beta);
+    return a;
+}
+
+SharedArgs shared_args(const Layout& L, void* ws) {
+    SharedArgs s{};
+    s.status = at<int32_t>(ws, L.status);
+    s.totals = at<double>(ws, L.totals);
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// Optional kernel timing (dcr_profile_*).
+// ---------------------------------------------------------------------------
+enum Kind { kKReduce = 0, kKCarries, kKMatW, kKMatU, kKMapFused, kKMapW, kNumKinds };
+const char* const kKindNames[kNumKinds] = {"reduce", "carries", "materialize_w",
+                                           "materialize_u", "map_fused", "map_w"};
+
+struct Profiler {
+    bool on = false;
+    int cap = 0;
+    int used = 0;
+    std::vector<hipEvent_t> ev;
+    std::vector<int> kind;
+};
+Profiler g_prof;
+
+template <class F>
+hipError_t timed(int kind, hipStream_t s, F&& launch) {
+    int slot = -1;
+    if (g_prof.on && g_prof.used < g_prof.cap) {
+        slot = g_prof.used++;
+        (void)hipEventRecord(g_prof.ev[2 * slot], s);
+    }
+    const hipError_t e = launch();
+    if (slot >= 0) {
+        (void)hipEventRecord(g_prof.ev[2 * slot + 1], s);
+        g_prof.kind[slot] = kind;
+    }
+    return e;
+}
+
+dcr_status hip_status(hipError_t e) { return e == hipSuccess ? DCR_OK : DCR_ERR_HIP; }
+
+}  // namespace
+
+extern "C" {
+
+const char* dcr_status_string(dcr_status s) {
+    switch (s) {
+        case DCR_OK: return "ok";
+        case DCR_ERR_INVALID_ARGUMENT: return "invalid argument";
+        case DCR_ERR_UNSUPPORTED: return "unsupported precision or option";
+        case DCR_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+        case DCR_ERR_CAPACITY_EXCEEDED: return "capacity exceeded";
+        case DCR_ERR_HIP: return "HIP runtime error";
+        case DCR_ERR_BAD_WEIGHTS: return "bad weights (negative, NaN, infinite or zero total)";
+        case DCR_ERR_INTERNAL: return "internal error";
+    }
+    return "unknown status";
+}
+
+dcr_status dcr_workspace_bytes(int64_t M, int64_t N, dcr_precision p, size_t* bytes) {
+    if (!bytes || M < 1 || M > kMaxM || N < 0 || N > kMaxN) return DCR_ERR_INVALID_ARGUMENT;
+    if (!valid_prec(p)) return DCR_ERR_UNSUPPORTED;
+    *bytes = make_layout(M, N, true).bytes;
+    return DCR_OK;
+}
+
+dcr_status dcr_cumulative_weights(const void* w, int64_t M, dcr_precision p, double* W,
+                                  double* total, int32_t* dev_status, void* ws, size_t ws_bytes,
+                                  hipStream_t stream) {
+    if (M < 1 || M > kMaxM || !w || !W || !ws) return DCR_ERR_INVALID_ARGUMENT;
+    if (!valid_prec(p)) return DCR_ERR_UNSUPPORTED;
+    if ((reinterpret_cast<uintptr_t>(ws) & 255u) != 0) return DCR_ERR_INVALID_ARGUMENT;
+    const Layout L = make_layout(M, 0, false);
+    if (ws_bytes < L.bytes) return DCR_ERR_WORKSPACE_TOO_SMALL;
+    const WArgs wa = w_args(L, ws, M);
+    ZArgs za{};
+    const SharedArgs sh = shared_args(L, ws);
+    const int prec = prec_code(p);
+    const int vec = (aligned16(w) ? 1 : 0) | (aligned16(W) ? 2 : 0);
+    hipError_t e = timed(kKReduce, stream, [&] { return dcr::launch_reduce(prec, w, wa, za, vec, stream); });
+    if (e == hipSuccess)
+        e = timed(kKCarries, stream,
+                  [&] { return dcr::launch_carries(wa, za, sh, dev_status, total, stream); });
+    if (e == hipSuccess)
+        e = timed(kKMatW, stream,
+                  [&] { return dcr::launch_materialize_w(prec, w, wa, sh, W, vec, stream); });
+    return hip_status(e);
+}
+
+dcr_status dcr_sorted_uniforms(int64_t N, uint64_t seed, uint64_t stream_id, dcr_precision p,
+                               double* u, void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (N < 0 || N > kMaxN) return DCR_ERR_INVALID_ARGUMENT;
+    if (!valid_prec(p)) return DCR_ERR_UNSUPPORTED;
+    if (N == 0) return DCR_OK;
+    if (!u || !ws || (reinterpret_cast<uintptr_t>(ws) & 255u) != 0) return DCR_ERR_INVALID_ARGUMENT;
+    const Layout L = make_layout(0, N, false);
+    if (ws_bytes < L.bytes) return DCR_ERR_WORKSPACE_TOO_SMALL;
+    WArgs wa{};
+    const ZArgs za = z_args(L, ws, N, seed, stream_id);
+    const SharedArgs sh = shared_args(L, ws);
+    const int prec = prec_code(p);
+    hipError_t e = timed(kKReduce, stream,
+                         [&] { return dcr::launch_reduce(prec, nullptr, wa, za, 0, stream); });
+    if (e == hipSuccess)
+        e = timed(kKCarries, stream,
+                  [&] { return dcr::launch_carries(wa, za, sh, nullptr, nullptr, stream); });
+    if (e == hipSuccess)
+        e = timed(kKMatU, stream, [&] { return dcr::launch_materialize_u(za, sh, u, stream); });
+    return hip_status(e);
+}
+
+dcr_status dcr_inverse_cmf(const double* W, int64_t M, const double* u, int64_t N, int32_t* r,
+                           void* ws, size_t ws_bytes, hipStream_t stream) {
+    (void)ws;
+    (void)ws_bytes;
+    if (M < 1 || M > kMaxM || N < 0 || N > kMaxN) return DCR_ERR_INVALID_ARGUMENT;
+    if (N == 0) return DCR_OK;
+    if (!W || !u || !r) return DCR_ERR_INVALID_ARGUMENT;
+    const hipError_t e =
+        timed(kKMapW, stream, [&] { return dcr::launch_map_w(W, M, u, N, r, stream); });
+    return hip_status(e);
+}
+
+dcr_status dcr_resample(const void* w, int64_t M, int64_t N, uint64_t seed, uint64_t stream_id,
+                        dcr_precision p, int32_t* r, double* W_opt, double* u_opt,
+                        int32_t* dev_status, void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (M < 1 || M > kMaxM || N < 0 || N > kMaxN || !w || !ws) return DCR_ERR_INVALID_ARGUMENT;
+    if (N > 0 && !r) return DCR_ERR_INVALID_ARGUMENT;
+    if (!valid_prec(p)) return DCR_ERR_UNSUPPORTED;
+    if ((reinterpret_cast<uintptr_t>(ws) & 255u) != 0) return DCR_ERR_INVALID_ARGUMENT;
+    const Layout L = make_layout(M, N, u_opt == nullptr);
+    if (ws_bytes < L.bytes) return DCR_ERR_WORKSPACE_TOO_SMALL;
+    const WArgs wa = w_args(L, ws, M);
+    const ZArgs za = z_args(L, ws, N, seed, stream_id);
+    const SharedArgs sh = shared_args(L, ws);
+    const int prec = prec_code(p);
+    const int vec = (aligned16(w) ? 1 : 0) | (aligned16(W_opt) ? 2 : 0);
+    double* u = u_opt ? u_opt : (N > 0 ? at<double>(ws, L.u_buf) : nullptr);
+    hipError_t e = timed(kKReduce, stream,
+                         [&] { return dcr::launch_reduce(prec, w, wa, za, vec, stream); });
+    if (e == hipSuccess)
+        e = timed(kKCarries, stream,
+                  [&] { return dcr::launch_carries(wa, za, sh, dev_status, nullptr, stream); });
+    if (e == hipSuccess && N > 0)
+        e = timed(kKMatU, stream, [&] { return dcr::launch_materialize_u(za, sh, u, stream); });
+    if (e == hipSuccess && W_opt)
+        e = timed(kKMatW, stream,
+                  [&] { return dcr::launch_materialize_w(prec, w, wa, sh, W_opt, vec, stream); });
+    if (e == hipSuccess && N > 0)
+        e = timed(kKMapFused, stream, [&] {
+            return dcr::launch_map_fused(prec, w, wa, sh, u, N, r, vec, stream);
+        });
+    return hip_status(e);
+}
+
+dcr_status dcr_profile_begin(int32_t cap) {
+    if (cap < 1 || g_prof.on) return DCR_ERR_INVALID_ARGUMENT;
+    g_prof.ev.assign(2 * static_cast<size_t>(cap), nullptr);
+    g_prof.kind.assign(cap, -1);
+    for (auto& ev : g_prof.ev)
+        if (hipEventCreate(&ev) != hipSuccess) return DCR_ERR_HIP;
+    g_prof.cap = cap;
+    g_prof.used = 0;
+    g_prof.on = true;
+    return DCR_OK;
+}
+
+dcr_status dcr_profile_end(int32_t n_kinds, int64_t* counts, double* ms) {
+    if (!g_prof.on) return DCR_ERR_INVALID_ARGUMENT;
+    g_prof.on = false;
+    dcr_status st = DCR_OK;
+    for (int k = 0; k < n_kinds; ++k) {
+        if (counts) counts[k] = 0;
+        if (ms) ms[k] = 0.0;
+    }
+    if (g_prof.used > 0 && hipEventSynchronize(g_prof.ev[2 * g_prof.used - 1]) != hipSuccess)
+        st = DCR_ERR_HIP;
+    for (int i = 0; i < g_prof.used && st == DCR_OK; ++i) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, g_prof.ev[2 * i], g_prof.ev[2 * i + 1]) != hipSuccess) {
+            st = DCR_ERR_HIP;
+            break;
+        }
+        const int k = g_prof.kind[i];
+        if (k >= 0 && k < n_kinds) {
+            if (counts) counts[k] += 1;
+            if (ms) ms[k] += t;
+        }
+    }
+    for (auto& ev : g_prof.ev)
+        if (ev) (void)hipEventDestroy(ev);
+    g_prof.ev.clear();
+    g_prof.kind.clear();
+    g_prof.used = 0;
+    g_prof.cap = 0;
+    return st;
+}
+
+int32_t dcr_profile_kind_count(void) { return kNumKinds; }
+
+const char* dcr_profile_kind_name(int32_t kind) {
+    return (kind >= 0 && kind < kNumKinds) ? kKindNames[kind] : "";
+}
+
+}  // extern "C"

@@ -1,0 +1,195 @@
+// dcr_device.hpp -- device-side building blocks shared by the libdcr kernels.
+//
+// Summation structure (defines the bits of W and u; every kernel that forms a
+// partial sum goes through the helpers below, so the bits agree everywhere):
+//
+//   lane chunk  16 consecutive elements, summed left to right:
+//               p(k) = (((x0 + x1) + x2) ... + xk)
+//   sub-tile    16 lane chunks = 256 elements; lane-chunk totals t_l combined
+//               left to right: c_0 = 0, c_{l+1} = c_l + t_l;
+//               in-sub-tile prefix q = c_l + p(k)  (equals c_{l+1} at k = 15)
+//   block       NS sub-tiles; sub-tile totals tau_s combined left to right:
+//               sigma_0 = 0, sigma_{s+1} = sigma_s + tau_s;
+//               in-block prefix S_blk = sigma_s + q  (equals sigma_{s+1} at the
+//               end of sub-tile s)
+//   array       block totals scanned by a monotone two-level scan (carries)
+//               into beta_1..beta_nb (beta_0 = 0, beta_nb = total);
+//               S_j = min(beta_b + S_blk, beta_{b+1}), and S_j = beta_{b+1} at
+//               the last element of block b.
+//
+// Every level either adds a non-negative local prefix to a base computed by
+// the same left-to-right rule (monotone because round-to-nearest is monotone)
+// or clamps to the next base, so S is non-decreasing and the end of every
+// segment equals the base of the next one.  Normalisation: W_j = S_j / total
+// (correctly rounded binary64 division; W_{M-1} = total / total = 1).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dcr_internal.hpp"
+
+namespace dcr {
+
+constexpr int kLane = 16;                 // elements per lane chunk
+constexpr int kRowLanes = 16;             // lane chunks per sub-tile
+constexpr int kSub = kLane * kRowLanes;   // 256 elements per sub-tile
+constexpr int kThreads = 256;             // threads per workgroup (16 rows)
+constexpr int kRows = kThreads / kRowLanes;
+constexpr int kWSubPerBlock = 128;        // sub-tiles per weight block
+constexpr int kWBlock = kWSubPerBlock * kSub;   // 32768 weights per block
+constexpr int kWIters = kWSubPerBlock / kRows;  // 8 sub-tile rounds per block
+constexpr int kZBlock = kThreads * kLane;       // 4096 spacings per block
+constexpr int kCarryThreads = 1024;
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of
+// (x0,x1,x2,x3) -> (hi(B*x2)^x1^k0, lo(B*x2), hi(A*x0)^x3^k1, lo(A*x0)) with
+// A = 0xD2511F53, B = 0xCD9E8D57 and the key advanced by the Weyl constants
+// 0x9E3779B9, 0xBB67AE85 between rounds.
+// ---------------------------------------------------------------------------
+struct Words4 {
+    uint32_t w0, w1, w2, w3;
+};
+
+__device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                                uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint32_t lo_a = 0xD2511F53u * c0;
+        const uint32_t hi_a = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo_b = 0xCD9E8D57u * c2;
+        const uint32_t hi_b = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = hi_b ^ c1 ^ k0;
+        const uint32_t n2 = hi_a ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo_b;
+        c2 = n2;
+        c3 = lo_a;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return Words4{c0, c1, c2, c3};
+}
+
+// Open-interval variate from 52 random bits: v = (2k + 1) * 2^-53, exact in
+// binary64 and inside [2^-53, 1 - 2^-53], so -log v is finite and positive.
+__device__ __forceinline__ double variate_from_words(uint32_t lo, uint32_t hi) {
+    const uint64_t k = (static_cast<uint64_t>(hi) << 20) | static_cast<uint64_t>(lo >> 12);
+    return static_cast<double>(2 * k + 1) * 0x1p-53;
+}
+
+// Exponential spacing z = -log v in the precision form P.
+template <int P>
+__device__ __forceinline__ double spacing_from_variate(double v) {
+    if constexpr (P == kPrecFP32) {
+        return static_cast<double>(-logf(static_cast<float>(v)));
+    } else {
+        return -log(v);
+    }
+}
+
+// Draws (2*pair, 2*pair + 1) of (seed, stream): one Philox block, words
+// (w0, w1) for the even draw and (w2, w3) for the odd draw.
+template <int P>
+__device__ __forceinline__ void spacing_pair(uint64_t pair, uint64_t seed, uint64_t stream,
+                                             double& z_even, double& z_odd) {
+    const Words4 x = philox4x32_10(static_cast<uint32_t>(pair), static_cast<uint32_t>(pair >> 32),
+                                   static_cast<uint32_t>(stream),
+                                   static_cast<uint32_t>(stream >> 32),
+                                   static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32));
+    z_even = spacing_from_variate<P>(variate_from_words(x.w0, x.w1));
+    z_odd = spacing_from_variate<P>(variate_from_words(x.w2, x.w3));
+}
+
+// ---------------------------------------------------------------------------
+// Loading one lane chunk of weights as binary64 (binary32 promoted exactly).
+// `n_valid` elements are real (0..16); the rest read as 0.  `vec_ok` allows
+// 16-byte vector loads (chunk fully valid and base pointer 16-byte aligned).
+// ---------------------------------------------------------------------------
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+template <typename Tin>
+__device__ __forceinline__ void load_chunk(const Tin* __restrict__ p, int n_valid, bool vec_ok,
+                                           double (&x)[kLane]) {
+    if (vec_ok && n_valid == kLane) {
+        if constexpr (sizeof(Tin) == 4) {
+            const f32x4* q = reinterpret_cast<const f32x4*>(p);
+            f32x4 f[kLane / 4];
+#pragma unroll
+            for (int v = 0; v < kLane / 4; ++v) f[v] = q[v];
+#pragma unroll
+            for (int v = 0; v < kLane / 4; ++v) {
+                x[4 * v + 0] = f[v].x;
+                x[4 * v + 1] = f[v].y;
+                x[4 * v + 2] = f[v].z;
+                x[4 * v + 3] = f[v].w;
+            }
+        } else {
+            const f64x2* q = reinterpret_cast<const f64x2*>(p);
+            f64x2 d[kLane / 2];
+#pragma unroll
+            for (int v = 0; v < kLane / 2; ++v) d[v] = q[v];
+#pragma unroll
+            for (int v = 0; v < kLane / 2; ++v) {
+                x[2 * v + 0] = d[v].x;
+                x[2 * v + 1] = d[v].y;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kLane; ++k) x[k] = (k < n_valid) ? static_cast<double>(p[k]) : 0.0;
+    }
+}
+
+// A weight is admissible iff it is finite and >= 0 (NaN fails both tests).
+__device__ __forceinline__ bool bad_weight(double x) { return !(x >= 0.0) || x == __builtin_huge_val(); }
+
+// Left-to-right sum of one lane chunk.
+__device__ __forceinline__ double chunk_sum(const double (&x)[kLane]) {
+    double s = x[0];
+#pragma unroll
+    for (int k = 1; k < kLane; ++k) s = s + x[k];
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// Normalisation threshold: the smallest binary64 x >= 0 with
+// fl(x / total) >= u, for 0 < u <= 1 and 0 < total < inf.  Because
+// x -> fl(x / total) is non-decreasing, fl(S / total) >= u  <=>  S >= x, so
+// every comparison of a normalised cumulative weight with u becomes a
+// comparison of an unnormalised partial sum with x.  fl(u * total) is within
+// two units in the last place of the answer, so the loops below take at most
+// a few steps; their bound only guards against misuse.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double next_up_nonneg(double x) {
+    return __longlong_as_double(__double_as_longlong(x) + 1);
+}
+__device__ __forceinline__ double next_down_pos(double x) {
+    return __longlong_as_double(__double_as_longlong(x) - 1);
+}
+
+__device__ __forceinline__ double threshold_for(double u, double total) {
+    double x = u * total;
+    if (x / total >= u) {
+        for (int it = 0; it < 64 && x > 0.0; ++it) {
+            const double d = next_down_pos(x);
+            if (d / total >= u)
+                x = d;
+            else
+                break;
+        }
+    } else {
+        for (int it = 0; it < 64; ++it) {
+            x = next_up_nonneg(x);
+            if (x / total >= u) break;
+        }
+    }
+    return x;
+}
+
+// Workgroup-wide logical OR (all threads must call it).
+__device__ __forceinline__ int block_any(int pred) { return __syncthreads_or(pred); }
+
+}  // namespace dcr

@@ -1,0 +1,116 @@
+"""The C ABI library loads, exports every entry point of include/dcr.h, and
+rejects bad arguments on the host before anything is enqueued (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dcr.h")
+LIB = os.path.join(ROOT, "paper_2604_01356_amd", "libdcr.so")
+
+FAKE = ctypes.c_void_p(0x7F0000000000)      # never dereferenced on the host
+FAKE_UNALIGNED = ctypes.c_void_p(0x7F0000000008)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.skip("libdcr.so not built")
+    import paper_2604_01356_amd as dcr
+    return dcr.library()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b(dcr_\w+)\s*\(",
+                                 text, re.M)))
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for n in ["dcr_workspace_bytes", "dcr_cumulative_weights", "dcr_sorted_uniforms",
+              "dcr_inverse_cmf", "dcr_resample", "dcr_status_string"]:
+        assert n in names
+
+
+def test_library_exports_every_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_status_strings(lib):
+    import paper_2604_01356_amd as dcr
+    for code in range(8):
+        assert dcr.dcr_status_string(code)
+    assert dcr.dcr_status_string(99) == "unknown status"
+
+
+def test_workspace_bytes(lib):
+    import paper_2604_01356_amd as dcr
+    a = dcr.dcr_workspace_bytes(1, 0)
+    b = dcr.dcr_workspace_bytes(1 << 20, 1 << 12)
+    c = dcr.dcr_workspace_bytes(1 << 26, 1 << 14, dcr.DCR_FP32_COMP)
+    assert 0 < a < b < c
+    assert c % 256 == 0
+    for bad in [(0, 0), (-1, 5), (1 << 31, 1), (10, -1), (10, 1 << 31)]:
+        with pytest.raises(dcr.DcrError) as e:
+            dcr.dcr_workspace_bytes(*bad)
+        assert e.value.code == 1
+    with pytest.raises(dcr.DcrError) as e:
+        dcr.dcr_workspace_bytes(10, 10, 7)
+    assert e.value.code == 2
+
+
+def _ws(lib, M, N):
+    n = ctypes.c_size_t(0)
+    assert lib.dcr_workspace_bytes(M, N, 0, ctypes.byref(n)) == 0
+    return n.value
+
+
+def test_host_validation_resample(lib):
+    ws = _ws(lib, 1000, 100)
+    f = lib.dcr_resample
+    # M out of range, NULL w, NULL ws, NULL r with N > 0
+    assert f(FAKE, 0, 100, 1, 0, 0, FAKE, None, None, None, FAKE, ws, None) == 1
+    assert f(None, 1000, 100, 1, 0, 0, FAKE, None, None, None, FAKE, ws, None) == 1
+    assert f(FAKE, 1000, 100, 1, 0, 0, FAKE, None, None, None, None, ws, None) == 1
+    assert f(FAKE, 1000, 100, 1, 0, 0, None, None, None, None, FAKE, ws, None) == 1
+    assert f(FAKE, 1000, -1, 1, 0, 0, FAKE, None, None, None, FAKE, ws, None) == 1
+    # unknown precision, unaligned or small workspace
+    assert f(FAKE, 1000, 100, 1, 0, 5, FAKE, None, None, None, FAKE, ws, None) == 2
+    assert f(FAKE, 1000, 100, 1, 0, 0, FAKE, None, None, None, FAKE_UNALIGNED, ws, None) == 1
+    assert f(FAKE, 1000, 100, 1, 0, 0, FAKE, None, None, None, FAKE, ws - 1, None) == 3
+
+
+def test_host_validation_stages(lib):
+    ws = _ws(lib, 1000, 100)
+    assert lib.dcr_cumulative_weights(FAKE, 0, 0, FAKE, None, None, FAKE, ws, None) == 1
+    assert lib.dcr_cumulative_weights(FAKE, 1000, 0, None, None, None, FAKE, ws, None) == 1
+    assert lib.dcr_cumulative_weights(FAKE, 1000, 3, FAKE, None, None, FAKE, ws, None) == 2
+    assert lib.dcr_cumulative_weights(FAKE, 1000, 0, FAKE, None, None, FAKE, 16, None) == 3
+    assert lib.dcr_sorted_uniforms(-1, 1, 0, 0, FAKE, FAKE, ws, None) == 1
+    assert lib.dcr_sorted_uniforms(100, 1, 0, 9, FAKE, FAKE, ws, None) == 2
+    assert lib.dcr_sorted_uniforms(100, 1, 0, 0, None, FAKE, ws, None) == 1
+    assert lib.dcr_sorted_uniforms(100, 1, 0, 0, FAKE, FAKE, 16, None) == 3
+    assert lib.dcr_sorted_uniforms(0, 1, 0, 0, None, None, 0, None) == 0   # N = 0: no-op
+    assert lib.dcr_inverse_cmf(FAKE, 0, FAKE, 10, FAKE, None, 0, None) == 1
+    assert lib.dcr_inverse_cmf(None, 10, FAKE, 10, FAKE, None, 0, None) == 1
+    assert lib.dcr_inverse_cmf(FAKE, 10, FAKE, 0, None, None, 0, None) == 0  # N = 0: no-op
+
+
+def test_profile_api_host(lib):
+    assert lib.dcr_profile_kind_count() >= 5
+    names = [lib.dcr_profile_kind_name(k).decode() for k in range(lib.dcr_profile_kind_count())]
+    assert "reduce" in names and "map_fused" in names
+    assert lib.dcr_profile_end(0, None, None) == 1   # not started
+    assert lib.dcr_profile_begin(0) == 1
+
+
+def test_package_fails_loudly_without_library(tmp_path, monkeypatch):
+    from paper_2604_01356_amd import _binding
+    monkeypatch.setattr(_binding, "_lib", None)
+    monkeypatch.setattr(_binding, "_LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError):
+        _binding.library()

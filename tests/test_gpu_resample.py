@@ -1,0 +1,157 @@
+"""End-to-end GPU resampling (dcr_resample) against the CPU oracle.
+
+- The fused end-to-end call must equal, bit for bit, stage 3 applied to the W
+  and u of stages 1 and 2 (and the oracle's exact map on those W and u).
+- Against the oracle's own end-to-end result, every index mismatch must be a
+  bin-edge case (the uniform lies within |du| + max|dW| + 1 ulp of an edge
+  separating the two indices); their number is reported.
+"""
+import numpy as np
+import pytest
+from scipy import stats
+
+import oracle
+import workloads
+from parity_util import assert_monotone_unit, classify_mismatches
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2604_01356_amd as dcr
+    dcr.library()
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def dcr():
+    import paper_2604_01356_amd as m
+    return m
+
+
+def _t(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def run_case(dcr, dev, w, N, seed, stream):
+    M = w.shape[0]
+    wt = _t(w, dev)
+    W = torch.empty(M, dtype=torch.float64, device=dev)
+    u = torch.empty(max(N, 1), dtype=torch.float64, device=dev)
+    st = torch.full((1,), -1, dtype=torch.int32, device=dev)
+    r = dcr.dcr_resample(wt, N, seed, stream, W_out=W, u_out=u, dev_status=st)
+    r_plain = dcr.dcr_resample(wt, N, seed, stream)        # W and u never written
+    W1 = dcr.dcr_cumulative_weights(wt)
+    prec = dcr.precision_of(wt)
+    u2 = dcr.dcr_sorted_uniforms(N, seed, stream, precision=prec, device=dev)
+    r3 = dcr.dcr_inverse_cmf(W1, u2)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    out = dict(r=r.cpu().numpy(), W=W.cpu().numpy(), u=u[:N].cpu().numpy(),
+               r_plain=r_plain.cpu().numpy(), W1=W1.cpu().numpy(), u2=u2.cpu().numpy(),
+               r3=r3.cpu().numpy())
+    # fused == staged, bit for bit
+    assert np.array_equal(out["r"], out["r_plain"])
+    assert np.array_equal(out["W"], out["W1"])
+    assert np.array_equal(out["u"], out["u2"])
+    assert np.array_equal(out["r"], out["r3"])
+    return out
+
+
+def check_against_oracle(out, w, N, seed, stream, du_cap, dW_cap):
+    r_o, W_o, u_o = oracle.resample(w, N, seed, stream)
+    assert_monotone_unit(out["W"])
+    if N:
+        assert np.all(np.diff(out["u"]) >= 0) and out["u"][0] > 0 and out["u"][-1] <= 1
+        assert np.all(np.diff(out["r"]) >= 0)
+        # the index map is exact on the GPU's own W and u
+        r_exact, _ = oracle.dac(out["W"], out["u"])
+        assert np.array_equal(out["r"], r_exact)
+    dW = np.max(np.abs(out["W"] - W_o))
+    du = np.max(np.abs(out["u"] - u_o)) if N else 0.0
+    assert dW <= dW_cap, dW
+    assert du <= du_cap, du
+    n_mis, bad = classify_mismatches(out["r"], r_o, out["u"], u_o, out["W"], W_o)
+    assert not bad, f"{len(bad)} mismatches away from bin edges, e.g. {bad[:5]}"
+    print(f"  M={len(w)} N={N} dW={dW:.2e} du={du:.2e} bin-edge mismatches={n_mis}", flush=True)
+    return n_mis
+
+
+# binary32 spacings: the two logf implementations are each within 1 ulp, so
+# |dz_i| <= 2^-22 z_i, |dZ_i| <= 2^-22 Z_i and |du_i| <= 2^-21 u_i.
+DU_FP32 = 2.0**-21
+
+RAGGED = [(1, 5), (3, 1), (5, 0), (100, 1000), (32769, 4097), (65537, 3), (40000, 4095),
+          (300001, 8191)]
+
+
+@pytest.mark.parametrize("M,N", RAGGED)
+def test_ragged_fp64(dev, dcr, M, N):
+    rng = np.random.default_rng(M + 31 * N)
+    w = np.exp(rng.normal(0, 2, M))
+    out = run_case(dcr, dev, w, N, seed=11, stream=2)
+    check_against_oracle(out, w, N, 11, 2, 1e-12, 2.0**-40)
+
+
+@pytest.mark.parametrize("M,N", RAGGED)
+def test_ragged_fp32(dev, dcr, M, N):
+    rng = np.random.default_rng(M + 37 * N)
+    w = np.exp(rng.normal(0, 2, M)).astype(np.float32)
+    out = run_case(dcr, dev, w, N, seed=12, stream=0)
+    # the oracle consumes the same binary32 weights promoted exactly, and the
+    # binary32 form of the spacings (z = -logf(fl32(v)))
+    check_against_oracle(out, w, N, 12, 0, DU_FP32, 2.0**-40)
+
+
+@pytest.mark.parametrize("maker", ["small_single", "engmf_step"])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_paper_shaped_configs(dev, dcr, maker, dtype):
+    wl = getattr(workloads, maker)()
+    w = wl.w64 if dtype == "f64" else wl.w32
+    out = run_case(dcr, dev, w, wl.N, seed=0, stream=0)
+    du_cap = 1e-12 if dtype == "f64" else DU_FP32
+    check_against_oracle(out, w, wl.N, 0, 0, du_cap, 2.0**-40)
+
+
+def test_zero_weight_bins_never_drawn(dev, dcr):
+    rng = np.random.default_rng(5)
+    w = np.exp(rng.normal(0, 1, 50000))
+    w[rng.random(50000) < 0.5] = 0.0
+    r = dcr.dcr_resample(_t(w, dev), 20000, seed=9).cpu().numpy()
+    assert np.all(w[r] > 0)
+
+
+def test_counts_chi_square_gpu(dev, dcr):
+    rng = np.random.default_rng(3)
+    M, N = 40, 200000
+    w = np.exp(rng.normal(0, 1, M))
+    r = dcr.dcr_resample(_t(w, dev), N, seed=17).cpu().numpy()
+    c = np.bincount(r, minlength=M)
+    assert stats.chisquare(c, N * w / w.sum()).pvalue > 1e-4
+
+
+def test_seed_and_stream_reproducible(dev, dcr):
+    w = _t(np.exp(np.random.default_rng(1).normal(0, 1, 10000)), dev)
+    a = dcr.dcr_resample(w, 3000, seed=5, stream_id=2).cpu().numpy()
+    b = dcr.dcr_resample(w, 3000, seed=5, stream_id=2).cpu().numpy()
+    c = dcr.dcr_resample(w, 3000, seed=5, stream_id=3).cpu().numpy()
+    assert np.array_equal(a, b) and not np.array_equal(a, c)
+
+
+@pytest.mark.parametrize("which", ["sparse", "equal"])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_full_size(dev, dcr, which, dtype):
+    """The large configurations at full size, in the benchmark's launch shape."""
+    wl = workloads.sparse_mass() if which == "sparse" else workloads.equal_size()
+    w = wl.w64 if dtype == "f64" else wl.w32
+    del wl
+    N = (1 << 14) if which == "sparse" else (1 << 24)
+    print(f"  full size {which} {dtype}: M={len(w)} N={N}", flush=True)
+    out = run_case(dcr, dev, w, N, seed=0, stream=0)
+    du_cap = 1e-12 if dtype == "f64" else DU_FP32
+    n_mis = check_against_oracle(out, w, N, 0, 0, du_cap, 2.0**-40)
+    assert n_mis <= max(10, N // 1000)
