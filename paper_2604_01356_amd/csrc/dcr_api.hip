@@ -27,7 +27,7 @@ size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 struct Layout {
     int64_t nwb = 0, nzb = 0;
     size_t status = 0, totals = 0;
-    size_t w_tot = 0, w_bad = 0, w_beta = 0, w_sub = 0;
+    size_t w_tot = 0, w_beta = 0, w_sub = 0;
     size_t z_tot = 0, z_beta = 0, z_buf = 0;
     size_t u_buf = 0;
     size_t bytes = 0;
@@ -44,8 +44,6 @@ Layout make_layout(int64_t M, int64_t N, bool want_u_buf) {
         L.nwb = (M + kWBlock - 1) / kWBlock;
         L.w_tot = off;
         off = align256(off + sizeof(double) * L.nwb);
-        L.w_bad = off;
-        off = align256(off + sizeof(int32_t) * L.nwb);
         L.w_beta = off;
         off = align256(off + sizeof(double) * L.nwb);
         L.w_sub = off;
@@ -82,7 +80,6 @@ WArgs w_args(const Layout& L, void* ws, int64_t M) {
     a.M = M;
     a.nb = L.nwb;
     a.blk_tot = at<double>(ws, L.w_tot);
-    a.blk_bad = at<int32_t>(ws, L.w_bad);
     a.beta = at<double>(ws, L.w_beta);
     a.sub_end = at<double>(ws, L.w_sub);
     return a;
@@ -94,7 +91,7 @@ ZArgs z_args(const Layout& L, void* ws, int64_t N, uint64_t seed, uint64_t strea
     a.nb = L.nzb;
     a.seed = seed;
     a.stream = stream;
-    a.zbuf = at<double>(ws, L.z_buf);
+    a.zrel = at<double>(ws, L.z_buf);
     a.blk_tot = at<double>(ws, L.z_tot);
     a.beta = at<double>(ws, L.z_beta);
     return a;
@@ -110,9 +107,9 @@ SharedArgs shared_args(const Layout& L, void* ws) {
 // ---------------------------------------------------------------------------
 // Optional kernel timing (dcr_profile_*).
 // ---------------------------------------------------------------------------
-enum Kind { kKReduce = 0, kKCarries, kKMatW, kKMatU, kKMapFused, kKMapW, kNumKinds };
-const char* const kKindNames[kNumKinds] = {"reduce", "carries", "materialize_w",
-                                           "materialize_u", "map_fused", "map_w"};
+enum Kind { kKReduce = 0, kKCarries, kKMatW, kKMatU, kKMapFused, kKMapW, kKFinish, kNumKinds };
+const char* const kKindNames[kNumKinds] = {"reduce", "carries", "materialize_w", "materialize_u",
+                                           "map_fused", "map_w", "finish"};
 
 struct Profiler {
     bool on = false;
@@ -239,6 +236,17 @@ dcr_status dcr_resample(const void* w, int64_t M, int64_t N, uint64_t seed, uint
     double* u = u_opt ? u_opt : (N > 0 ? at<double>(ws, L.u_buf) : nullptr);
     hipError_t e = timed(kKReduce, stream,
                          [&] { return dcr::launch_reduce(prec, w, wa, za, vec, stream); });
+    if (dcr::finish_fits(wa, za)) {
+        // block scans, uniforms and map in one launch
+        if (e == hipSuccess)
+            e = timed(kKFinish, stream, [&] {
+                return dcr::launch_finish(prec, w, wa, za, sh, dev_status, u_opt, r, vec, stream);
+            });
+        if (e == hipSuccess && W_opt)
+            e = timed(kKMatW, stream,
+                      [&] { return dcr::launch_materialize_w(prec, w, wa, sh, W_opt, vec, stream); });
+        return hip_status(e);
+    }
     if (e == hipSuccess)
         e = timed(kKCarries, stream,
                   [&] { return dcr::launch_carries(wa, za, sh, dev_status, nullptr, stream); });

@@ -143,6 +143,54 @@ __device__ __forceinline__ void load_chunk(const Tin* __restrict__ p, int n_vali
     }
 }
 
+// A full, 16-byte aligned lane chunk kept unconverted in registers between
+// its load and its use, so that loads of later chunks can be issued first.
+template <typename Tin>
+struct RawChunk;
+
+template <>
+struct RawChunk<float> {
+    f32x4 v[kLane / 4];
+    __device__ __forceinline__ double at(int k) const { return static_cast<double>(v[k >> 2][k & 3]); }
+    __device__ __forceinline__ float raw(int k) const { return v[k >> 2][k & 3]; }
+};
+
+template <>
+struct RawChunk<double> {
+    f64x2 v[kLane / 2];
+    __device__ __forceinline__ double at(int k) const { return v[k >> 1][k & 1]; }
+    __device__ __forceinline__ double raw(int k) const { return v[k >> 1][k & 1]; }
+};
+
+template <typename Tin>
+__device__ __forceinline__ RawChunk<Tin> load_raw(const Tin* __restrict__ p) {
+    RawChunk<Tin> r;
+    if constexpr (sizeof(Tin) == 4) {
+        const f32x4* q = reinterpret_cast<const f32x4*>(p);
+#pragma unroll
+        for (int v = 0; v < kLane / 4; ++v) r.v[v] = q[v];
+    } else {
+        const f64x2* q = reinterpret_cast<const f64x2*>(p);
+#pragma unroll
+        for (int v = 0; v < kLane / 2; ++v) r.v[v] = q[v];
+    }
+    return r;
+}
+
+// Left-to-right binary64 sum of a raw chunk; also folds its elements into a
+// running minimum (in the input precision) used to detect negative weights.
+template <typename Tin>
+__device__ __forceinline__ double raw_sum(const RawChunk<Tin>& r, Tin& mn) {
+    double s = r.at(0);
+    mn = fmin(mn, r.raw(0));
+#pragma unroll
+    for (int k = 1; k < kLane; ++k) {
+        s = s + r.at(k);
+        mn = fmin(mn, r.raw(k));
+    }
+    return s;
+}
+
 // A weight is admissible iff it is finite and >= 0 (NaN fails both tests).
 __device__ __forceinline__ bool bad_weight(double x) { return !(x >= 0.0) || x == __builtin_huge_val(); }
 
@@ -189,7 +237,83 @@ __device__ __forceinline__ double threshold_for(double u, double total) {
     return x;
 }
 
+// ---------------------------------------------------------------------------
+// Cross-lane moves with DPP (register speed, no LDS round trip).  Lanes whose
+// source lies outside the pattern receive 0, the identity of the sums and of
+// the maxima of non-negative values used here.
+// ---------------------------------------------------------------------------
+template <int CTRL, int ROWMASK = 0xF>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWMASK, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWMASK, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+
+constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
+constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143, kDppWaveShr1 = 0x138;
+constexpr int kDppQuadSwap1 = 0xB1;   // quad_perm [1,0,3,2]
+constexpr int kDppQuadSwap2 = 0x4E;   // quad_perm [2,3,0,1]
+constexpr int kDppQuadBcast(int k) { return k * 0x55; }   // quad_perm [k,k,k,k]
+
+// Inclusive scans over the 64 lanes of a wave (rows of 16 by doubling shifts,
+// then the row carries by broadcast of lanes 15 and 31).
+__device__ __forceinline__ double wave_incl_add(double v) {
+    v = v + dpp_f64<kDppRowShr1>(v);
+    v = v + dpp_f64<kDppRowShr2>(v);
+    v = v + dpp_f64<kDppRowShr4>(v);
+    v = v + dpp_f64<kDppRowShr8>(v);
+    v = v + dpp_f64<kDppRowBcast15, 0xA>(v);
+    v = v + dpp_f64<kDppRowBcast31, 0xC>(v);
+    return v;
+}
+
+__device__ __forceinline__ double wave_incl_max(double v) {
+    v = fmax(v, dpp_f64<kDppRowShr1>(v));
+    v = fmax(v, dpp_f64<kDppRowShr2>(v));
+    v = fmax(v, dpp_f64<kDppRowShr4>(v));
+    v = fmax(v, dpp_f64<kDppRowShr8>(v));
+    v = fmax(v, dpp_f64<kDppRowBcast15, 0xA>(v));
+    v = fmax(v, dpp_f64<kDppRowBcast31, 0xC>(v));
+    return v;
+}
+
+// The value of the previous lane (0 in lane 0).
+__device__ __forceinline__ double wave_shift_up1(double v) { return dpp_f64<kDppWaveShr1>(v); }
+
+// Value of lane k of this lane's quad, for a quad-uniform k in 0..3.
+__device__ __forceinline__ double quad_bcast(double v, int k) {
+    const double v0 = dpp_f64<kDppQuadBcast(0)>(v);
+    const double v1 = dpp_f64<kDppQuadBcast(1)>(v);
+    const double v2 = dpp_f64<kDppQuadBcast(2)>(v);
+    const double v3 = dpp_f64<kDppQuadBcast(3)>(v);
+    return k == 0 ? v0 : (k == 1 ? v1 : (k == 2 ? v2 : v3));
+}
+
+// Sum of an integer over the 4 lanes of a quad.
+__device__ __forceinline__ int quad_sum(int v) {
+    v += dpp_i32<kDppQuadSwap1>(v);
+    v += dpp_i32<kDppQuadSwap2>(v);
+    return v;
+}
+
 // Workgroup-wide logical OR (all threads must call it).
 __device__ __forceinline__ int block_any(int pred) { return __syncthreads_or(pred); }
+
+// Workgroup barrier that orders LDS accesses only: outstanding global loads
+// and stores stay in flight across it.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+constexpr int kDppWaveShl1 = 0x130;
+// The value of the next lane (0 in lane 63).
+__device__ __forceinline__ double wave_shift_down1(double v) { return dpp_f64<kDppWaveShl1>(v); }
 
 }  // namespace dcr

@@ -17,8 +17,7 @@ constexpr int kStatusBadWeights = 6;
 struct WArgs {
     int64_t M;
     int64_t nb;
-    double* blk_tot;   // [nb]   block totals
-    int32_t* blk_bad;  // [nb]   1 if the block holds an inadmissible weight
+    double* blk_tot;   // [nb]   block totals (NaN: the block holds an inadmissible weight)
     double* beta;      // [nb]   block ends beta_1..beta_nb (monotone scan)
     double* sub_end;   // [nb*128] in-block sub-tile ends sigma_1..sigma_128
 };
@@ -29,7 +28,7 @@ struct ZArgs {
     int64_t nb;
     uint64_t seed;
     uint64_t stream;
-    double* zbuf;      // [N+1] spacings
+    double* zrel;      // [N+1] in-block prefix sums of the spacings
     double* blk_tot;   // [nb]
     double* beta;      // [nb]
 };
@@ -41,8 +40,16 @@ struct SharedArgs {
 
 hipError_t launch_reduce(int prec, const void* w, const WArgs& wa, const ZArgs& za, int vec_ok,
                          hipStream_t s);
+// k_finish handles up to 4096 weight blocks (M <= 2^27) and this many
+// spacing blocks (N + 1 <= 2^18).
+constexpr int kFinishMaxZBlocks = 64;
+bool finish_fits(const WArgs& wa, const ZArgs& za);
+
 hipError_t launch_carries(const WArgs& wa, const ZArgs& za, const SharedArgs& sh,
                           int32_t* dev_status, double* total_out, hipStream_t s);
+hipError_t launch_finish(int prec, const void* w, const WArgs& wa, const ZArgs& za,
+                         const SharedArgs& sh, int32_t* dev_status, double* u_out, int32_t* r,
+                         int vec_ok, hipStream_t s);
 hipError_t launch_materialize_w(int prec, const void* w, const WArgs& wa, const SharedArgs& sh,
                                 double* W, int vec_ok, hipStream_t s);
 hipError_t launch_materialize_u(const ZArgs& za, const SharedArgs& sh, double* u, hipStream_t s);

@@ -5,6 +5,8 @@
 //   k_carries           monotone scans of the block totals, totals, validity
 //   k_materialize_w     normalised cumulative weights W (stage 1 output)
 //   k_materialize_u     sorted uniforms u (stage 2 output)
+//   k_finish            block scans + uniforms + map in one launch (the common
+//                       end-to-end case)
 //   k_map_fused         inverse CMF of u against the cumulative weights kept
 //                       implicit (block bases + sub-tile bases + a rescan of one
 //                       256-weight sub-tile), the divide-and-conquer map of
@@ -24,50 +26,100 @@ __device__ __forceinline__ int clamp_count(int64_t remaining, int cap) {
 // ---------------------------------------------------------------------------
 // k_reduce: blocks [0, za.nb) draw spacings, blocks [za.nb, za.nb + wa.nb)
 // reduce weights.
+//
+// Binary32 weights in a full block stream through LDS: each wave's 4 KB round
+// (its 4 sub-tiles, 64 lanes x 16 consecutive weights) is fetched with
+// coalesced direct-to-LDS loads two rounds ahead, then every lane reads its own
+// 16 consecutive weights back.  Lane-strided global loads of the same bytes
+// reach only ~85% of the coalesced bandwidth on this chip.
 // ---------------------------------------------------------------------------
+constexpr int kStreamDepth = 2;                     // rounds in flight beyond the current
+constexpr int kStreamBufs = kStreamDepth + 1;
+constexpr int kWaveRoundF32 = 64 * kLane;           // floats per wave per round (4 KB)
+constexpr int kWaves = kThreads / 64;
+
+// Three separate LDS objects hold the stream buffers (separate objects let
+// the compiler see that reading one buffer need not wait for the loads still
+// in flight into another); the block epilogue reuses the first one.
+template <typename Tin>
+struct ReduceSmem {
+    static constexpr int kBuf = (sizeof(Tin) == 4) ? kWaves * kWaveRoundF32 * 4 : 16;
+    static constexpr int kEpi = (kWIters * kThreads + 2 * kWSubPerBlock) * 8;
+    static constexpr int kBuf0 = kBuf > kEpi ? kBuf : kEpi;
+};
+
+__device__ __forceinline__ void wait_vm(int outstanding) {
+    // s_waitcnt with vmcnt = outstanding (0..15), expcnt and lgkmcnt left at max
+    __builtin_amdgcn_sched_barrier(0);
+    if (outstanding >= 8)
+        __builtin_amdgcn_s_waitcnt(0x0F78);
+    else if (outstanding >= 4)
+        __builtin_amdgcn_s_waitcnt(0x0F74);
+    else
+        __builtin_amdgcn_s_waitcnt(0x0F70);
+    __builtin_amdgcn_sched_barrier(0);
+}
+
 template <typename Tin, int P>
 __global__ __launch_bounds__(kThreads) void k_reduce(const Tin* __restrict__ w, WArgs wa, ZArgs za,
                                                      int vec_ok) {
-    __shared__ double lane_tot[kWIters * kThreads];
-    __shared__ double sub_tot[kWSubPerBlock];
-    __shared__ double sub_end[kWSubPerBlock];
+    __shared__ __attribute__((aligned(16))) unsigned char sb0[ReduceSmem<Tin>::kBuf0];
+    __shared__ __attribute__((aligned(16))) unsigned char sb1[ReduceSmem<Tin>::kBuf];
+    __shared__ __attribute__((aligned(16))) unsigned char sb2[ReduceSmem<Tin>::kBuf];
+    double* lane_tot = reinterpret_cast<double*>(sb0);   // [kWIters][kThreads]
+    double* sub_tot = lane_tot + kWIters * kThreads;      // [kWSubPerBlock]
+    double* sub_end = sub_tot + kWSubPerBlock;            // [kWSubPerBlock]
     const int t = threadIdx.x;
     const int row = t / kRowLanes;
     const int lane = t % kRowLanes;
 
     if (static_cast<int64_t>(blockIdx.x) < za.nb) {
-        // ---- exponential spacings z_i = -log v_i, i = 0..N (Alg. 1) ----
+        // ---- exponential spacings z_i = -log v_i, i = 0..N (Alg. 1), and
+        //      their in-block prefix sums (stored) and block total ----
         const int64_t g = blockIdx.x;
         const int64_t i0 = g * kZBlock + static_cast<int64_t>(t) * kLane;
         const int nv = clamp_count(za.N + 1 - i0, kLane);
-        double z[kLane];
+        double p[kLane];
 #pragma unroll
         for (int k = 0; k < kLane; k += 2) {
             double ze = 0.0, zo = 0.0;
             if (k < nv) spacing_pair<P>(static_cast<uint64_t>(i0 + k) >> 1, za.seed, za.stream, ze, zo);
-            z[k] = (k < nv) ? ze : 0.0;
-            z[k + 1] = (k + 1 < nv) ? zo : 0.0;
+            p[k] = (k < nv) ? ze : 0.0;
+            p[k + 1] = (k + 1 < nv) ? zo : 0.0;
         }
-        if (nv == kLane) {
-            f64x2* q = reinterpret_cast<f64x2*>(za.zbuf + i0);
 #pragma unroll
-            for (int v = 0; v < kLane / 2; ++v) q[v] = f64x2{z[2 * v], z[2 * v + 1]};
+        for (int k = 1; k < kLane; ++k) p[k] = p[k - 1] + p[k];
+        lane_tot[t] = p[kLane - 1];
+        lds_barrier();
+        double lv[kRowLanes];
+#pragma unroll
+        for (int k = 0; k < kRowLanes; ++k) lv[k] = lane_tot[row * kRowLanes + k];
+        double c = 0.0;
+#pragma unroll
+        for (int k = 0; k < kRowLanes; ++k)
+            if (k < lane) c = c + lv[k];
+        if (lane == kRowLanes - 1) sub_tot[row] = c + lv[kRowLanes - 1];
+        lds_barrier();
+        double rv[kRows];
+#pragma unroll
+        for (int k = 0; k < kRows; ++k) rv[k] = sub_tot[k];
+        double sigma = 0.0, total = 0.0;
+#pragma unroll
+        for (int k = 0; k < kRows; ++k) {
+            if (k < row) sigma = sigma + rv[k];
+            total = total + rv[k];
+        }
+        double zr[kLane];
+#pragma unroll
+        for (int k = 0; k < kLane; ++k) zr[k] = sigma + (c + p[k]);
+        if (nv == kLane) {
+            f64x2* q = reinterpret_cast<f64x2*>(za.zrel + i0);
+#pragma unroll
+            for (int v = 0; v < kLane / 2; ++v) q[v] = f64x2{zr[2 * v], zr[2 * v + 1]};
         } else {
-            for (int k = 0; k < nv; ++k) za.zbuf[i0 + k] = z[k];
+            for (int k = 0; k < nv; ++k) za.zrel[i0 + k] = zr[k];
         }
-        lane_tot[t] = chunk_sum(z);
-        __syncthreads();
-        if (t < kRows) {
-            double c = lane_tot[t * kRowLanes];
-            for (int l = 1; l < kRowLanes; ++l) c = c + lane_tot[t * kRowLanes + l];
-            sub_tot[t] = c;
-        }
-        __syncthreads();
-        if (t == 0) {
-            double s = 0.0;
-            for (int r = 0; r < kRows; ++r) s = s + sub_tot[r];
-            za.blk_tot[g] = s;
-        }
+        if (t == 0) za.blk_tot[g] = total;
         return;
     }
 
@@ -75,113 +127,318 @@ __global__ __launch_bounds__(kThreads) void k_reduce(const Tin* __restrict__ w, 
     const int64_t b = static_cast<int64_t>(blockIdx.x) - za.nb;
     const int64_t blk0 = b * kWBlock;
     int bad = 0;
-    // two rounds of loads in flight per wave keeps the register count low
-    // enough for several waves per SIMD
-#pragma unroll 2
-    for (int it = 0; it < kWIters; ++it) {
-        const int64_t j0 = blk0 + static_cast<int64_t>(it * kRows + row) * kSub + lane * kLane;
-        const int nv = clamp_count(wa.M - j0, kLane);
-        double x[kLane];
-        load_chunk<Tin>(w + (nv > 0 ? j0 : 0), nv, (vec_ok & 1) != 0, x);
+    double lt[kWIters];
+    const bool full = (vec_ok & 1) && blk0 + kWBlock <= wa.M;
+    if constexpr (sizeof(Tin) == 4) {
+        if (full) {
+            float* const bufs[kStreamBufs] = {reinterpret_cast<float*>(sb0),
+                                              reinterpret_cast<float*>(sb1),
+                                              reinterpret_cast<float*>(sb2)};
+            const int wv = t >> 6;
+            const int l64 = t & 63;
+            // the wave's rows 4wv..4wv+3 of round `it` are kWaveRoundF32 consecutive weights
+            const float* src = reinterpret_cast<const float*>(w) + blk0 + wv * kWaveRoundF32;
+            auto issue = [&](int it) {
+                float* dst = bufs[it % kStreamBufs] + wv * kWaveRoundF32;
+                const float* g0 = src + it * (kWaves * kWaveRoundF32);
 #pragma unroll
-        for (int k = 0; k < kLane; ++k) bad |= bad_weight(x[k]) ? 1 : 0;
-        lane_tot[it * kThreads + t] = chunk_sum(x);
+                for (int k = 0; k < kLane / 4; ++k)
+                    __builtin_amdgcn_global_load_lds(g0 + k * 256 + l64 * 4, dst + k * 256, 16, 0, 0);
+            };
+            float mn = 0.0f;
+#pragma unroll
+            for (int it = 0; it < kStreamDepth; ++it) issue(it);
+#pragma unroll
+            for (int it = 0; it < kWIters; ++it) {
+                if (it + kStreamDepth < kWIters) {
+                    issue(it + kStreamDepth);
+                    wait_vm(kStreamDepth * (kLane / 4));
+                } else {
+                    wait_vm((kWIters - 1 - it) * (kLane / 4));
+                }
+                __builtin_amdgcn_wave_barrier();
+                const f32x4* mine = reinterpret_cast<const f32x4*>(
+                    bufs[it % kStreamBufs] + wv * kWaveRoundF32 + l64 * kLane);
+                RawChunk<float> rc;
+#pragma unroll
+                for (int k = 0; k < kLane / 4; ++k) rc.v[k] = mine[k];
+                if (it == 0) mn = rc.raw(0);
+                lt[it] = raw_sum<float>(rc, mn);
+                __builtin_amdgcn_sched_barrier(0);
+                __builtin_amdgcn_wave_barrier();
+            }
+            // NaN and +inf reach the block total (checked below); negatives the minimum
+            bad = (mn < 0.0f) ? 1 : 0;
+        }
+    } else {
+        if (full) {
+            // binary64: lane-strided loads, the next round issued before summing
+            const Tin* base = w + blk0 + row * kSub + lane * kLane;
+            Tin mn = static_cast<Tin>(0);
+            RawChunk<Tin> cur = load_raw<Tin>(base);
+            mn = cur.raw(0);
+#pragma unroll
+            for (int it = 0; it < kWIters; ++it) {
+                RawChunk<Tin> nxt;
+                if (it + 1 < kWIters) nxt = load_raw<Tin>(base + (it + 1) * kRows * kSub);
+                lt[it] = raw_sum<Tin>(cur, mn);
+                if (it + 1 < kWIters) cur = nxt;
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            bad = (mn < static_cast<Tin>(0)) ? 1 : 0;
+        }
     }
+    if (!full) {
+#pragma unroll 1
+        for (int it = 0; it < kWIters; ++it) {
+            const int64_t j0 = blk0 + static_cast<int64_t>(it * kRows + row) * kSub + lane * kLane;
+            const int nv = clamp_count(wa.M - j0, kLane);
+            double x[kLane];
+            load_chunk<Tin>(w + (nv > 0 ? j0 : 0), nv, (vec_ok & 1) != 0, x);
+#pragma unroll
+            for (int k = 0; k < kLane; ++k) bad |= bad_weight(x[k]) ? 1 : 0;
+            const double ct = chunk_sum(x);
+#pragma unroll
+            for (int q = 0; q < kWIters; ++q)
+                if (q == it) lt[q] = ct;
+        }
+    }
+    lds_barrier();   // the first stream buffer becomes the epilogue's scratch
+#pragma unroll
+    for (int it = 0; it < kWIters; ++it) lane_tot[it * kThreads + t] = lt[it];
     bad = block_any(bad);
     if (t < kWSubPerBlock) {
         const int it = t / kRows;
         const int r = t % kRows;
         const double* p = lane_tot + it * kThreads + r * kRowLanes;
-        double c = p[0];
-        for (int l = 1; l < kRowLanes; ++l) c = c + p[l];
+        double lv[kRowLanes];
+#pragma unroll
+        for (int l = 0; l < kRowLanes; ++l) lv[l] = p[l];
+        double c = lv[0];
+#pragma unroll
+        for (int l = 1; l < kRowLanes; ++l) c = c + lv[l];
         sub_tot[t] = c;
     }
-    __syncthreads();
+    lds_barrier();
     if (t == 0) {
         double s = 0.0;
+#pragma unroll 16
         for (int q = 0; q < kWSubPerBlock; ++q) {
             s = s + sub_tot[q];
             sub_end[q] = s;
         }
     }
-    __syncthreads();
+    lds_barrier();
     if (t < kWSubPerBlock) wa.sub_end[b * kWSubPerBlock + t] = sub_end[t];
     if (t == 0) {
-        wa.blk_tot[b] = sub_end[kWSubPerBlock - 1];
-        wa.blk_bad[b] = bad;
+        // an inadmissible block (negative weight, NaN, infinity or overflow)
+        // publishes a NaN total, which every scan of the totals detects
+        const double tot = sub_end[kWSubPerBlock - 1];
+        wa.blk_tot[b] = (bad || !(tot < __builtin_huge_val())) ? __builtin_nan("") : tot;
     }
 }
 
 // ---------------------------------------------------------------------------
-// Monotone two-level scan run by a whole 1024-thread workgroup:
-//   thread t owns a contiguous range, sums it left to right (p), group-of-32
-//   exclusive bases h are left-to-right sums of thread totals, group bases G
-//   are left-to-right sums of group totals, gamma_t = G + h, and
-//   out_j = min(gamma_t + p_j, gamma_{t+1}).
-// out is non-decreasing for non-negative input.  Returns out[n-1] to every
-// thread (0 for n == 0).
+// Monotone scans of block totals by the 256 threads of one workgroup, two at a
+// time (weights and spacings share the barriers).  The same code runs in
+// every kernel that needs a scan, so the results agree bit for bit.
+// For one sequence of n totals: thread t owns a contiguous range and sums it
+// left to right (p_j); the thread bases gamma_t are an exclusive scan of the
+// thread totals (DPP wave scans, then the 4 wave totals left to right) made
+// non-decreasing by a running maximum; then
+//     out_j = min(gamma_t + p_j, gamma_{t+1}),
+// which is non-decreasing for non-negative input.  A NaN or infinite total
+// (an inadmissible block) sets the sequence's `bad` flag.
 // ---------------------------------------------------------------------------
-__device__ double monotone_scan(const double* __restrict__ in, int64_t n, double* __restrict__ out,
-                                double* T, double* GT, double* gam, double* bcast) {
+constexpr int kScanThreads = kThreads;
+constexpr int kScanWaves = kScanThreads / 64;
+constexpr int kScanRegs = 16;   // ranges up to this length stay in registers
+
+// Per-thread inputs of a scan, loaded ahead of the computation so that the
+// loads of both scans (and of other data) are in flight together.
+struct ScanIn {
+    int64_t a, e;
+    bool in_regs;
+    double v[kScanRegs];
+};
+
+struct ScanOut {
+    const double* in;   // the totals (re-read when they do not fit in registers)
+    int64_t n;
+    double* out_lds;    // may be null
+    double* out_gl;     // may be null
+};
+
+struct ScanLds {
+    double wtot[2][kScanWaves];
+    double wmax[2][kScanWaves];
+    int wbad[2][kScanWaves];
+    double last[2];
+};
+
+__device__ __forceinline__ void scan_load(const double* __restrict__ in, int64_t n, ScanIn& si) {
     const int t = threadIdx.x;
-    const int64_t per = (n + kCarryThreads - 1) / kCarryThreads;
-    const int64_t a = (static_cast<int64_t>(t) * per < n) ? static_cast<int64_t>(t) * per : n;
-    const int64_t e = (a + per < n) ? a + per : n;
-    double tt = 0.0;
-    for (int64_t j = a; j < e; ++j) tt = tt + in[j];
-    T[t] = tt;
-    __syncthreads();
-    const int g = t / 32;
-    const int q = t % 32;
-    double h = 0.0;
-    for (int k = 0; k < q; ++k) h = h + T[g * 32 + k];
-    if (q == 31) GT[g] = h + T[t];
-    __syncthreads();
-    double G = 0.0;
-    for (int k = 0; k < g; ++k) G = G + GT[k];
-    const double gamma = G + h;
-    gam[t] = gamma;
-    if (t == 0) gam[kCarryThreads] = __builtin_huge_val();
-    __syncthreads();
-    const double gnext = gam[t + 1];
-    double p = 0.0;
-    for (int64_t j = a; j < e; ++j) {
-        p = p + in[j];
-        const double v = fmin(gamma + p, gnext);
-        out[j] = v;
-        if (j == n - 1) *bcast = v;
+    const int64_t per = (n + kScanThreads - 1) / kScanThreads;
+    si.a = (static_cast<int64_t>(t) * per < n) ? static_cast<int64_t>(t) * per : n;
+    si.e = (si.a + per < n) ? si.a + per : n;
+    si.in_regs = per <= kScanRegs;
+    if (si.in_regs) {
+#pragma unroll
+        for (int k = 0; k < kScanRegs; ++k) si.v[k] = (si.a + k < si.e) ? in[si.a + k] : 0.0;
     }
-    if (n == 0 && t == 0) *bcast = 0.0;
-    __syncthreads();
-    const double r = *bcast;
-    __syncthreads();
-    return r;
 }
 
-__global__ __launch_bounds__(kCarryThreads) void k_carries(WArgs wa, ZArgs za, SharedArgs sh,
-                                                           int32_t* dev_status, double* total_out) {
-    __shared__ double T[kCarryThreads];
-    __shared__ double GT[kCarryThreads / 32];
-    __shared__ double gam[kCarryThreads + 1];
-    __shared__ double bcast;
+// Computes both scans; total[k] = out[n-1] of sequence k (0 if n == 0).
+__device__ void scan_pair(const ScanIn (&si)[2], const ScanOut (&so)[2], ScanLds& L,
+                          double (&total)[2], int (&bad)[2]) {
     const int t = threadIdx.x;
-    int status = kStatusOk;
-    if (wa.nb > 0) {
-        int bad = 0;
-        for (int64_t b = t; b < wa.nb; b += kCarryThreads) bad |= wa.blk_bad[b];
-        bad = block_any(bad);
-        const double tot = monotone_scan(wa.blk_tot, wa.nb, wa.beta, T, GT, gam, &bcast);
-        if (bad || !(tot > 0.0) || tot == __builtin_huge_val()) status = kStatusBadWeights;
-        if (t == 0) {
-            sh.totals[0] = tot;
-            if (total_out) *total_out = tot;
+    const int lane64 = t & 63;
+    const int wid = t >> 6;
+    double excl[2], wmx[2], wb[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        double tt = 0.0;
+        int nonfinite = 0;
+        if (si[q].in_regs) {
+#pragma unroll
+            for (int k = 0; k < kScanRegs; ++k) {
+                tt = tt + si[q].v[k];   // + 0.0 past the range is exact
+                nonfinite |= !(si[q].v[k] < __builtin_huge_val());
+            }
+        } else {
+            for (int64_t j = si[q].a; j < si[q].e; ++j) {
+                const double x = so[q].in[j];
+                tt = tt + x;
+                nonfinite |= !(x < __builtin_huge_val());
+            }
         }
+        const double incl = wave_incl_add(tt);
+        excl[q] = wave_shift_up1(incl);
+        const bool wave_bad = __builtin_amdgcn_ballot_w64(nonfinite != 0) != 0;
+        if (lane64 == 63) L.wtot[q][wid] = incl;
+        if (lane64 == 0) L.wbad[q][wid] = wave_bad ? 1 : 0;
     }
-    if (za.nb > 0) {
-        const double ztot = monotone_scan(za.blk_tot, za.nb, za.beta, T, GT, gam, &bcast);
-        if (t == 0) sh.totals[1] = ztot;
+    lds_barrier();
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        double w4[kScanWaves];
+        int b4 = 0;
+#pragma unroll
+        for (int k = 0; k < kScanWaves; ++k) {
+            w4[k] = L.wtot[q][k];
+            b4 |= L.wbad[q][k];
+        }
+        bad[q] = b4;
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < kScanWaves; ++k)
+            if (k < wid) s = s + w4[k];
+        wb[q] = s;
+        wmx[q] = wave_incl_max(s + excl[q]);
+        if (lane64 == 63) L.wmax[q][wid] = wmx[q];
     }
+    lds_barrier();
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        double m4[kScanWaves], w4[kScanWaves];
+#pragma unroll
+        for (int k = 0; k < kScanWaves; ++k) {
+            m4[k] = L.wmax[q][k];
+            w4[k] = L.wtot[q][k];
+        }
+        double prev = 0.0, prev_next = 0.0;
+#pragma unroll
+        for (int k = 0; k < kScanWaves; ++k) {
+            if (k < wid) prev = fmax(prev, m4[k]);
+            if (k <= wid) prev_next = fmax(prev_next, m4[k]);
+        }
+        const double gamma = fmax(wmx[q], prev);
+        // base of the next thread: the next lane's, or for lane 63 the base of
+        // the next wave's lane 0, fmax(wave base, running maximum so far)
+        double gnext = wave_shift_down1(gamma);
+        if (lane64 == 63) {
+            double wbn = wb[q];
+#pragma unroll
+            for (int k = 0; k < kScanWaves; ++k)
+                if (k == wid) wbn = wbn + w4[k];
+            gnext = (wid == kScanWaves - 1) ? __builtin_huge_val() : fmax(wbn, prev_next);
+        }
+        const int64_t a = si[q].a, e = si[q].e, n = so[q].n;
+        double p = 0.0;
+        if (si[q].in_regs) {
+#pragma unroll
+            for (int k = 0; k < kScanRegs; ++k) {
+                if (a + k < e) {
+                    p = p + si[q].v[k];
+                    const double o = fmin(gamma + p, gnext);
+                    if (so[q].out_lds) so[q].out_lds[a + k] = o;
+                    if (so[q].out_gl) so[q].out_gl[a + k] = o;
+                    if (a + k == n - 1) L.last[q] = o;
+                }
+            }
+        } else {
+            for (int64_t j = a; j < e; ++j) {
+                p = p + so[q].in[j];
+                const double o = fmin(gamma + p, gnext);
+                if (so[q].out_lds) so[q].out_lds[j] = o;
+                if (so[q].out_gl) so[q].out_gl[j] = o;
+                if (j == n - 1) L.last[q] = o;
+            }
+        }
+        if (n == 0 && t == 0) L.last[q] = 0.0;
+    }
+    lds_barrier();
+    total[0] = L.last[0];
+    total[1] = L.last[1];
+}
+
+// ---------------------------------------------------------------------------
+// Sorted uniforms from the stored in-block prefixes: for draw i in spacing
+// block g,  Z_i = min(beta_g + Zrel_i, beta_{g+1})  (Z_i = beta_{g+1} at the
+// block's last draw) and  u_i = Z_i / Z_N.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double uniform_of(double zrel, int64_t i, int64_t N, double beta_g,
+                                             double beta_n, double ztot) {
+    const int64_t g = i / kZBlock;
+    const int64_t ilast = (g * kZBlock + kZBlock - 1 < N) ? g * kZBlock + kZBlock - 1 : N;
+    const double Z = (i == ilast) ? beta_n : fmin(beta_g + zrel, beta_n);
+    return Z / ztot;
+}
+
+__device__ __forceinline__ void store_uniforms(double* __restrict__ u, int64_t i0, int nout,
+                                               const double (&out)[kLane], int vec_out) {
+    if (nout == kLane && vec_out) {
+        f64x2* q = reinterpret_cast<f64x2*>(u + i0);
+#pragma unroll
+        for (int v = 0; v < kLane / 2; ++v) q[v] = f64x2{out[2 * v], out[2 * v + 1]};
+    } else {
+        for (int k = 0; k < nout; ++k) u[i0 + k] = out[k];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_carries: block-total scans (weights and spacings), totals and validity.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kScanThreads) void k_carries(WArgs wa, ZArgs za, SharedArgs sh,
+                                                          int32_t* dev_status, double* total_out) {
+    __shared__ ScanLds L;
+    const int t = threadIdx.x;
+    ScanIn si[2];
+    scan_load(wa.blk_tot, wa.nb, si[0]);
+    scan_load(za.blk_tot, za.nb, si[1]);
+    const ScanOut so[2] = {{wa.blk_tot, wa.nb, nullptr, wa.beta}, {za.blk_tot, za.nb, nullptr, za.beta}};
+    double tot[2];
+    int bad[2];
+    scan_pair(si, so, L, tot, bad);
     if (t == 0) {
+        int status = kStatusOk;
+        if (wa.nb > 0) {
+            if (bad[0] || !(tot[0] > 0.0) || !(tot[0] < __builtin_huge_val()))
+                status = kStatusBadWeights;
+            sh.totals[0] = tot[0];
+            if (total_out) *total_out = tot[0];
+        }
+        if (za.nb > 0) sh.totals[1] = tot[1];
         sh.status[0] = status;
         if (dev_status) *dev_status = status;
     }
@@ -211,9 +468,14 @@ __global__ __launch_bounds__(kThreads) void k_materialize_w(const Tin* __restric
 #pragma unroll
     for (int k = 1; k < kLane; ++k) p[k] = p[k - 1] + x[k];
     lane_tot[t] = p[kLane - 1];
-    __syncthreads();
+    lds_barrier();
+    double lv[kRowLanes];
+#pragma unroll
+    for (int k = 0; k < kRowLanes; ++k) lv[k] = lane_tot[row * kRowLanes + k];
     double c = 0.0;
-    for (int l = 0; l < lane; ++l) c = c + lane_tot[row * kRowLanes + l];
+#pragma unroll
+    for (int k = 0; k < kRowLanes; ++k)
+        if (k < lane) c = c + lv[k];
     if (nv == 0 || sh.status[0] != kStatusOk) return;
     const double sigma = (s == 0) ? 0.0 : wa.sub_end[b * kWSubPerBlock + s - 1];
     const double beta_b = (b == 0) ? 0.0 : wa.beta[b - 1];
@@ -236,84 +498,65 @@ __global__ __launch_bounds__(kThreads) void k_materialize_w(const Tin* __restric
 }
 
 // ---------------------------------------------------------------------------
-// k_materialize_u: one workgroup per spacing block of 4096 draws.
+// k_materialize_u: one workgroup per spacing block of 4096 draws, 16 per thread.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kThreads) void k_materialize_u(ZArgs za, SharedArgs sh,
                                                             double* __restrict__ u, int vec_out) {
-    __shared__ double lane_tot[kThreads];
-    __shared__ double row_tot[kRows];
-    const int t = threadIdx.x;
-    const int row = t / kRowLanes;
-    const int lane = t % kRowLanes;
     const int64_t g = blockIdx.x;
-    const int64_t i0 = g * kZBlock + static_cast<int64_t>(t) * kLane;
-    const int nv = clamp_count(za.N + 1 - i0, kLane);
-    double p[kLane];
-    if (nv == kLane) {
-        const f64x2* q = reinterpret_cast<const f64x2*>(za.zbuf + i0);
+    const double beta_g = (g == 0) ? 0.0 : za.beta[g - 1];
+    const double beta_n = za.beta[g];
+    const double ztot = sh.totals[1];
+    const int64_t i0 = g * kZBlock + static_cast<int64_t>(threadIdx.x) * kLane;
+    const int nout = clamp_count(za.N - i0, kLane);   // draws i < N are output
+    double zr[kLane];
+    if (nout == kLane) {
+        const f64x2* q = reinterpret_cast<const f64x2*>(za.zrel + i0);
 #pragma unroll
         for (int v = 0; v < kLane / 2; ++v) {
             const f64x2 d = q[v];
-            p[2 * v] = d.x;
-            p[2 * v + 1] = d.y;
+            zr[2 * v] = d.x;
+            zr[2 * v + 1] = d.y;
         }
     } else {
 #pragma unroll
-        for (int k = 0; k < kLane; ++k) p[k] = (k < nv) ? za.zbuf[i0 + k] : 0.0;
+        for (int k = 0; k < kLane; ++k) zr[k] = (k < nout) ? za.zrel[i0 + k] : 0.0;
     }
-#pragma unroll
-    for (int k = 1; k < kLane; ++k) p[k] = p[k - 1] + p[k];
-    lane_tot[t] = p[kLane - 1];
-    __syncthreads();
-    double c = 0.0;
-    for (int l = 0; l < lane; ++l) c = c + lane_tot[row * kRowLanes + l];
-    if (lane == kRowLanes - 1) row_tot[row] = c + lane_tot[t];
-    __syncthreads();
-    double sigma = 0.0;
-    for (int r = 0; r < row; ++r) sigma = sigma + row_tot[r];
-    const double beta_g = (g == 0) ? 0.0 : za.beta[g - 1];
-    const double beta_n = za.beta[g];
-    const int64_t ilast = (g * kZBlock + kZBlock - 1 < za.N) ? g * kZBlock + kZBlock - 1 : za.N;
-    const double ztot = sh.totals[1];
-    const int nout = clamp_count(za.N - i0, kLane);   // draws i < N are output
     double out[kLane];
 #pragma unroll
-    for (int k = 0; k < kLane; ++k) {
-        const double Z = (i0 + k == ilast) ? beta_n : fmin(beta_g + (sigma + (c + p[k])), beta_n);
-        out[k] = Z / ztot;
-    }
-    if (nout == kLane && vec_out) {
-        f64x2* q = reinterpret_cast<f64x2*>(u + i0);
-#pragma unroll
-        for (int v = 0; v < kLane / 2; ++v) q[v] = f64x2{out[2 * v], out[2 * v + 1]};
-    } else {
-        for (int k = 0; k < nout; ++k) u[i0 + k] = out[k];
-    }
+    for (int k = 0; k < kLane; ++k) out[k] = uniform_of(zr[k], i0 + k, za.N, beta_g, beta_n, ztot);
+    store_uniforms(u, i0, nout, out, vec_out);
 }
 
 // ---------------------------------------------------------------------------
-// Inverse CMF against implicit cumulative weights.  For each uniform u the
-// threshold x (S >= x  <=>  W >= u) is located level by level, as the
-// divide-and-conquer sampler narrows its ranges (Alg. 5): first the block
-// (search of the block ends beta), then the sub-tile (search of the stored
-// sub-tile ends), then the lane chunk and the element by re-summing the one
-// 256-weight sub-tile with the same left-to-right rule as k_reduce.
+// Inverse CMF against implicit cumulative weights, one uniform per quad of 4
+// lanes.  The threshold x (S >= x  <=>  W >= u) is located level by level, as
+// the divide-and-conquer sampler narrows its ranges (Alg. 5): the block
+// (search of the block ends held in LDS, `sbeta`, every kstride-th end), the
+// sub-tile (each lane of the quad reads a quarter of the block's stored
+// sub-tile ends), the lane chunk (each lane re-sums a quarter of the one
+// 256-weight sub-tile with the left-to-right rule of k_reduce) and the element.
+// Each level costs one round trip to memory.
 // ---------------------------------------------------------------------------
+constexpr int kBetaLds = 4096;
+constexpr int kQuad = 4;
+constexpr int kUPerWG = kThreads / kQuad;
+
 template <typename Tin>
-__global__ __launch_bounds__(kThreads) void k_map_fused(const Tin* __restrict__ w, WArgs wa,
-                                                        SharedArgs sh, const double* __restrict__ u,
-                                                        int64_t N, int32_t* __restrict__ r,
-                                                        int vec_ok) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
-    if (i >= N) return;
-    if (sh.status[0] != kStatusOk) {
-        r[i] = -1;
-        return;
+__device__ void map_quad(const Tin* __restrict__ w, const WArgs& wa, const double* sbeta,
+                         int64_t kstride, int ns, double x, int64_t i, int qi,
+                         int32_t* __restrict__ r, int vec_ok) {
+    const int64_t nb = wa.nb;
+    // ---- block level: first b with beta_{b+1} >= x ----
+    int qlo = 0, qhi = ns - 1;
+    while (qlo < qhi) {
+        const int mid = (qlo + qhi) >> 1;
+        if (sbeta[mid] < x)
+            qlo = mid + 1;
+        else
+            qhi = mid;
     }
-    const double total = sh.totals[0];
-    const double x = threshold_for(u[i], total);
-    // block level: first b with beta_{b+1} >= x
-    int64_t lo = 0, hi = wa.nb - 1;
+    int64_t lo = static_cast<int64_t>(qlo) * kstride;
+    int64_t hi = ((static_cast<int64_t>(qlo) + 1) * kstride < nb ? (qlo + 1) * kstride : nb) - 1;
     while (lo < hi) {
         const int64_t mid = (lo + hi) >> 1;
         if (wa.beta[mid] < x)
@@ -322,79 +565,205 @@ __global__ __launch_bounds__(kThreads) void k_map_fused(const Tin* __restrict__ 
             hi = mid;
     }
     const int64_t b = lo;
-    const double beta_b = (b == 0) ? 0.0 : wa.beta[b - 1];
-    const double beta_n = wa.beta[b];
+    const double beta_b =
+        (b == 0) ? 0.0 : ((b % kstride == 0) ? sbeta[b / kstride - 1] : wa.beta[b - 1]);
+    const double beta_n = (kstride == 1) ? sbeta[b] : wa.beta[b];
     const int64_t blk0 = b * kWBlock;
     const int64_t blen = (wa.M - blk0 < kWBlock) ? wa.M - blk0 : kWBlock;
     const int64_t jlast = blk0 + blen - 1;
     const int nsub = static_cast<int>((blen + kSub - 1) / kSub);
     const double* se = wa.sub_end + b * kWSubPerBlock;
-    // sub-tile level: first s with end(s) >= x
-    int slo = 0, shi = nsub - 1;
-    while (slo < shi) {
-        const int mid = (slo + shi) >> 1;
-        const double e = fmin(beta_b + se[mid], beta_n);
-        if (e < x)
-            slo = mid + 1;
-        else
-            shi = mid;
+    // ---- sub-tile level: first s with end(s) >= x, where
+    //      end(s) = min(beta_b + sigma_{s+1}, beta_{b+1}) and end(nsub-1) = beta_{b+1};
+    //      lane qi counts the ends below x among sub-tiles 32qi .. 32qi+31 ----
+    constexpr int kPerLane = kWSubPerBlock / kQuad;
+    const int s0 = kPerLane * qi;
+    double e[kPerLane];
+    if (s0 + kPerLane - 1 < nsub - 1) {
+        const f64x2* q = reinterpret_cast<const f64x2*>(se + s0);
+#pragma unroll
+        for (int v = 0; v < kPerLane / 2; ++v) {
+            const f64x2 d = q[v];
+            e[2 * v] = d.x;
+            e[2 * v + 1] = d.y;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kPerLane; ++k) e[k] = (s0 + k < nsub - 1) ? se[s0 + k] : 0.0;
     }
-    const int s = slo;
-    const double sigma = (s == 0) ? 0.0 : se[s - 1];
+    int cnt = 0;
+#pragma unroll
+    for (int k = 0; k < kPerLane; ++k)
+        cnt += (s0 + k < nsub - 1 && fmin(beta_b + e[k], beta_n) < x) ? 1 : 0;
+    const int s = quad_sum(cnt);
+    // sigma_s = stored end of sub-tile s-1, taken from the lane that read it
+    double sig = 0.0;
+#pragma unroll
+    for (int k = 0; k < kPerLane; ++k)
+        if (s0 + k == s - 1) sig = e[k];
+    const double sigma = (s == 0) ? 0.0 : quad_bcast(sig, (s - 1) / kPerLane);
     const int64_t sub0 = blk0 + static_cast<int64_t>(s) * kSub;
     const int slen = static_cast<int>((jlast - sub0 + 1 < kSub) ? jlast - sub0 + 1 : kSub);
     const int nl = (slen + kLane - 1) / kLane;
-    // lane level: lane-chunk totals, left to right, four chunks in flight
-    const bool last_sub = (s == nsub - 1);   // its last chunk ends at beta_{b+1}
-    int lf = -1;
-    double c = 0.0, cf = 0.0, cprev = 0.0;
-    for (int l4 = 0; l4 < nl && lf < 0; l4 += 4) {
-        double lt[4];
+    // ---- lane-chunk level: lane qi sums chunks 4qi .. 4qi+3 ----
+    constexpr int kChunks = kRowLanes / kQuad;
+    double tl[kChunks];
+    const bool full_sub = (slen == kSub) && (vec_ok & 1);
+    RawChunk<Tin> rc[kChunks];
+    if (full_sub) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int l = l4 + q;
+        for (int q = 0; q < kChunks; ++q)
+            rc[q] = load_raw<Tin>(w + sub0 + (kChunks * qi + q) * kLane);
+#pragma unroll
+        for (int q = 0; q < kChunks; ++q) {
+            Tin mn = static_cast<Tin>(0);
+            tl[q] = raw_sum<Tin>(rc[q], mn);
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < kChunks; ++q) {
+            const int l = kChunks * qi + q;
             const int nv = (l < nl) ? ((slen - l * kLane < kLane) ? slen - l * kLane : kLane) : 0;
             double xx[kLane];
             load_chunk<Tin>(w + (nv > 0 ? sub0 + l * kLane : 0), nv, (vec_ok & 1) != 0, xx);
-            lt[q] = chunk_sum(xx);
+            tl[q] = chunk_sum(xx);
         }
+    }
+    // every lane of the quad gets the 16 chunk totals and runs the
+    // left-to-right chunk bases c_l to find the first chunk ending at >= x
+    double tall[kRowLanes];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int l = l4 + q;
-            if (l < nl && lf < 0) {
-                const double cn = c + lt[q];
-                const double e =
-                    (last_sub && l == nl - 1) ? beta_n : fmin(beta_b + (sigma + cn), beta_n);
-                if (e >= x) {
-                    lf = l;
-                    cf = c;
-                }
-                cprev = c;
-                c = cn;
+    for (int q = 0; q < kChunks; ++q) {
+        tall[q] = dpp_f64<kDppQuadBcast(0)>(tl[q]);
+        tall[kChunks + q] = dpp_f64<kDppQuadBcast(1)>(tl[q]);
+        tall[2 * kChunks + q] = dpp_f64<kDppQuadBcast(2)>(tl[q]);
+        tall[3 * kChunks + q] = dpp_f64<kDppQuadBcast(3)>(tl[q]);
+    }
+    const bool last_sub = (s == nsub - 1);   // its last chunk ends at beta_{b+1}
+    int lf = -1;
+    double c = 0.0, cf = 0.0, cprev = 0.0;
+#pragma unroll
+    for (int l = 0; l < kRowLanes; ++l) {
+        if (l < nl && lf < 0) {
+            const double cn = c + tall[l];
+            const double en =
+                (last_sub && l == nl - 1) ? beta_n : fmin(beta_b + (sigma + cn), beta_n);
+            if (en >= x) {
+                lf = l;
+                cf = c;
             }
+            cprev = c;
+            c = cn;
         }
     }
     if (lf < 0) {  // unreachable: the sub-tile's end is >= x by the search above
         lf = nl - 1;
         cf = cprev;
     }
-    // element level
+    if (qi != lf / kChunks) return;
+    // ---- element level, by the lane that summed chunk lf ----
     const int64_t l0 = sub0 + static_cast<int64_t>(lf) * kLane;
     const int nv = (slen - lf * kLane < kLane) ? slen - lf * kLane : kLane;
     double xx[kLane];
-    load_chunk<Tin>(w + l0, nv, (vec_ok & 1) != 0, xx);
+    if (full_sub) {   // the chunk is still in registers
+        RawChunk<Tin> sel = rc[0];
+#pragma unroll
+        for (int q = 1; q < kChunks; ++q)
+            if (q == lf % kChunks) sel = rc[q];
+#pragma unroll
+        for (int k = 0; k < kLane; ++k) xx[k] = sel.at(k);
+    } else {
+        load_chunk<Tin>(w + l0, nv, (vec_ok & 1) != 0, xx);
+    }
     double pk = 0.0;
     int64_t jr = l0 + nv - 1;
     for (int k = 0; k < nv; ++k) {
         pk = pk + xx[k];
         const int64_t j = l0 + k;
-        const double e = (j == jlast) ? beta_n : fmin(beta_b + (sigma + (cf + pk)), beta_n);
-        if (e >= x) {
+        const double en = (j == jlast) ? beta_n : fmin(beta_b + (sigma + (cf + pk)), beta_n);
+        if (en >= x) {
             jr = j;
             break;
         }
     }
     r[i] = static_cast<int32_t>(jr);
+}
+
+// Map with the scanned block ends read from memory (after k_carries).
+template <typename Tin>
+__global__ __launch_bounds__(kThreads) void k_map_fused(const Tin* __restrict__ w, WArgs wa,
+                                                        SharedArgs sh, const double* __restrict__ u,
+                                                        int64_t N, int32_t* __restrict__ r,
+                                                        int vec_ok) {
+    __shared__ double sbeta[kBetaLds];
+    const int t = threadIdx.x;
+    const int64_t nb = wa.nb;
+    const int64_t kstride = (nb + kBetaLds - 1) / kBetaLds;
+    const int ns = static_cast<int>((nb + kstride - 1) / kstride);
+    for (int q = t; q < ns; q += kThreads) {
+        const int64_t b = (static_cast<int64_t>(q) + 1) * kstride - 1;
+        sbeta[q] = wa.beta[b < nb ? b : nb - 1];
+    }
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kUPerWG + (t / kQuad);
+    const bool ok = sh.status[0] == kStatusOk;
+    const double x = (i < N && ok) ? threshold_for(u[i], sh.totals[0]) : 0.0;
+    lds_barrier();
+    if (i >= N) return;   // the four lanes of a quad share i
+    if (!ok) {
+        if ((t & (kQuad - 1)) == 0) r[i] = -1;
+        return;
+    }
+    map_quad<Tin>(w, wa, sbeta, kstride, ns, x, i, t & (kQuad - 1), r, vec_ok);
+}
+
+// ---------------------------------------------------------------------------
+// k_finish: everything after k_reduce in one launch, for up to 4096 weight
+// blocks and 64 spacing blocks.  Every workgroup scans the block totals itself
+// (the same scan as k_carries, so the same bits), forms the uniforms of its 64
+// draws and maps them; workgroup 0 also publishes the scans, totals and status.
+// ---------------------------------------------------------------------------
+template <typename Tin>
+__global__ __launch_bounds__(kThreads) void k_finish(const Tin* __restrict__ w, WArgs wa, ZArgs za,
+                                                     SharedArgs sh, int32_t* dev_status,
+                                                     double* __restrict__ u_out,
+                                                     int32_t* __restrict__ r, int vec_ok) {
+    __shared__ double sbeta[kBetaLds];
+    __shared__ double szbeta[kFinishMaxZBlocks];
+    __shared__ ScanLds L;
+    const int t = threadIdx.x;
+    const int qi = t & (kQuad - 1);
+    const bool lead = blockIdx.x == 0;
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kUPerWG + (t / kQuad);
+    // every independent load first: the block totals of both scans and the
+    // in-block spacing prefix of this quad's draw
+    ScanIn si[2];
+    scan_load(wa.blk_tot, wa.nb, si[0]);
+    scan_load(za.blk_tot, za.nb, si[1]);
+    const double zrel = (i < za.N) ? za.zrel[i] : 0.0;
+    const ScanOut so[2] = {{wa.blk_tot, wa.nb, sbeta, lead ? wa.beta : nullptr},
+                           {za.blk_tot, za.nb, szbeta, lead ? za.beta : nullptr}};
+    double tt[2];
+    int bad[2];
+    scan_pair(si, so, L, tt, bad);
+    const double tot = tt[0], ztot = tt[1];
+    const int status =
+        (bad[0] || !(tot > 0.0) || !(tot < __builtin_huge_val())) ? kStatusBadWeights : kStatusOk;
+    if (lead && t == 0) {
+        sh.status[0] = status;
+        sh.totals[0] = tot;
+        sh.totals[1] = ztot;
+        if (dev_status) *dev_status = status;
+    }
+    if (i >= za.N) return;   // the four lanes of a quad share i
+    const int64_t g = i / kZBlock;
+    const double uu = uniform_of(zrel, i, za.N, (g == 0) ? 0.0 : szbeta[g - 1], szbeta[g], ztot);
+    if (u_out && qi == 0) u_out[i] = uu;
+    if (status != kStatusOk) {
+        if (qi == 0) r[i] = -1;
+        return;
+    }
+    const double x = threshold_for(uu, tot);
+    map_quad<Tin>(w, wa, sbeta, 1, static_cast<int>(wa.nb), x, i, qi, r, vec_ok);
 }
 
 // ---------------------------------------------------------------------------
@@ -425,7 +794,7 @@ __global__ __launch_bounds__(kThreads) void k_map_w(const double* __restrict__ W
     const int64_t last = (first + kThreads < N ? first + kThreads : N) - 1;
     if (t == 0) range[0] = lower_bound_clamped(W, 0, M - 1, u[first]);
     if (t == 1) range[1] = lower_bound_clamped(W, 0, M - 1, u[last]);
-    __syncthreads();
+    lds_barrier();
     const int64_t i = first + t;
     if (i <= last) r[i] = static_cast<int32_t>(lower_bound_clamped(W, range[0], range[1], u[i]));
 }
@@ -451,7 +820,7 @@ hipError_t launch_reduce(int prec, const void* w, const WArgs& wa, const ZArgs& 
 
 hipError_t launch_carries(const WArgs& wa, const ZArgs& za, const SharedArgs& sh,
                           int32_t* dev_status, double* total_out, hipStream_t s) {
-    hipLaunchKernelGGL(k_carries, dim3(1), dim3(kCarryThreads), 0, s, wa, za, sh, dev_status,
+    hipLaunchKernelGGL(k_carries, dim3(1), dim3(kScanThreads), 0, s, wa, za, sh, dev_status,
                        total_out);
     return hipGetLastError();
 }
@@ -480,13 +849,31 @@ hipError_t launch_materialize_u(const ZArgs& za, const SharedArgs& sh, double* u
 hipError_t launch_map_fused(int prec, const void* w, const WArgs& wa, const SharedArgs& sh,
                             const double* u, int64_t N, int32_t* r, int vec_ok, hipStream_t s) {
     if (N <= 0) return hipSuccess;
-    const int64_t grid = (N + kThreads - 1) / kThreads;
+    const int64_t grid = (N + kUPerWG - 1) / kUPerWG;
     if (prec == kPrecFP32)
         hipLaunchKernelGGL(k_map_fused<float>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0,
                            s, static_cast<const float*>(w), wa, sh, u, N, r, vec_ok);
     else
         hipLaunchKernelGGL(k_map_fused<double>, dim3(static_cast<unsigned>(grid)), dim3(kThreads),
                            0, s, static_cast<const double*>(w), wa, sh, u, N, r, vec_ok);
+    return hipGetLastError();
+}
+
+bool finish_fits(const WArgs& wa, const ZArgs& za) {
+    return za.N > 0 && wa.nb >= 1 && wa.nb <= kBetaLds && za.nb >= 1 && za.nb <= kFinishMaxZBlocks;
+}
+
+hipError_t launch_finish(int prec, const void* w, const WArgs& wa, const ZArgs& za,
+                         const SharedArgs& sh, int32_t* dev_status, double* u_out, int32_t* r,
+                         int vec_ok, hipStream_t s) {
+    const int64_t grid = (za.N + kUPerWG - 1) / kUPerWG;
+    if (prec == kPrecFP32)
+        hipLaunchKernelGGL(k_finish<float>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s,
+                           static_cast<const float*>(w), wa, za, sh, dev_status, u_out, r, vec_ok);
+    else
+        hipLaunchKernelGGL(k_finish<double>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0,
+                           s, static_cast<const double*>(w), wa, za, sh, dev_status, u_out, r,
+                           vec_ok);
     return hipGetLastError();
 }
 

@@ -85,8 +85,10 @@ def check_against_oracle(out, w, N, seed, stream, du_cap, dW_cap):
 # |dz_i| <= 2^-22 z_i, |dZ_i| <= 2^-22 Z_i and |du_i| <= 2^-21 u_i.
 DU_FP32 = 2.0**-21
 
+# (M, N): ragged edges of lanes, sub-tiles, blocks and spacing blocks; the
+# last two take the multi-launch path (N + 1 > 2^18 spacings)
 RAGGED = [(1, 5), (3, 1), (5, 0), (100, 1000), (32769, 4097), (65537, 3), (40000, 4095),
-          (300001, 8191)]
+          (300001, 8191), (100003, 262143), (70001, 300000)]
 
 
 @pytest.mark.parametrize("M,N", RAGGED)
@@ -140,6 +142,16 @@ def test_seed_and_stream_reproducible(dev, dcr):
     b = dcr.dcr_resample(w, 3000, seed=5, stream_id=2).cpu().numpy()
     c = dcr.dcr_resample(w, 3000, seed=5, stream_id=3).cpu().numpy()
     assert np.array_equal(a, b) and not np.array_equal(a, c)
+
+
+def test_many_blocks_sampled_index(dev, dcr):
+    """More than 4096 weight blocks (M > 2^27): the map keeps every second block
+    end in LDS and finishes the block search in memory."""
+    M = (1 << 27) + 12345
+    rng = np.random.default_rng(99)
+    w = np.exp(rng.normal(0, 4, M)).astype(np.float32)
+    out = run_case(dcr, dev, w, 5000, seed=4, stream=1)
+    check_against_oracle(out, w, 5000, 4, 1, DU_FP32, 2.0**-40)
 
 
 @pytest.mark.parametrize("which", ["sparse", "equal"])
