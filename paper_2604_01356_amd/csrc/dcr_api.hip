@@ -20,20 +20,21 @@ constexpr int64_t kMaxN = 2147483646LL;   // N + 1 draws must stay below 2^31
 constexpr int64_t kWBlock = 32768;
 constexpr int64_t kWSubPerBlock = 128;
 constexpr int64_t kZBlock = 4096;
+constexpr int64_t kDenseU = 4096;   // uniforms per workgroup of the dense map
 
 size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
-// Workspace layout: [header][weight side][spacing side][uniforms]
 struct Layout {
     int64_t nwb = 0, nzb = 0;
     size_t status = 0, totals = 0;
     size_t w_tot = 0, w_beta = 0, w_sub = 0;
     size_t z_tot = 0, z_beta = 0, z_buf = 0;
-    size_t u_buf = 0;
+    size_t wide = 0;
     size_t bytes = 0;
 };
 
-Layout make_layout(int64_t M, int64_t N, bool want_u_buf) {
+// Workspace layout: [header][weight side][spacing side][dense-map flags]
+Layout make_layout(int64_t M, int64_t N) {
     Layout L;
     size_t off = 0;
     L.status = off;
@@ -57,10 +58,8 @@ Layout make_layout(int64_t M, int64_t N, bool want_u_buf) {
         off = align256(off + sizeof(double) * L.nzb);
         L.z_buf = off;
         off = align256(off + sizeof(double) * L.nzb * kZBlock);
-        if (want_u_buf) {
-            L.u_buf = off;
-            off = align256(off + sizeof(double) * N);
-        }
+        L.wide = off;
+        off = align256(off + sizeof(int32_t) * ((N + kDenseU - 1) / kDenseU));
     }
     L.bytes = off;
     return L;
@@ -107,9 +106,11 @@ SharedArgs shared_args(const Layout& L, void* ws) {
 // ---------------------------------------------------------------------------
 // Optional kernel timing (dcr_profile_*).
 // ---------------------------------------------------------------------------
-enum Kind { kKReduce = 0, kKCarries, kKMatW, kKMatU, kKMapFused, kKMapW, kKFinish, kNumKinds };
-const char* const kKindNames[kNumKinds] = {"reduce", "carries", "materialize_w", "materialize_u",
-                                           "map_fused", "map_w", "finish"};
+enum Kind {
+    kKReduce = 0, kKCarries, kKMatW, kKMatU, kKMapFused, kKMapW, kKFinish, kKMapDense, kNumKinds
+};
+const char* const kKindNames[kNumKinds] = {"reduce",   "carries", "materialize_w", "materialize_u",
+                                           "map_fused", "map_w",  "finish",        "map_dense"};
 
 struct Profiler {
     bool on = false;
@@ -158,7 +159,7 @@ const char* dcr_status_string(dcr_status s) {
 dcr_status dcr_workspace_bytes(int64_t M, int64_t N, dcr_precision p, size_t* bytes) {
     if (!bytes || M < 1 || M > kMaxM || N < 0 || N > kMaxN) return DCR_ERR_INVALID_ARGUMENT;
     if (!valid_prec(p)) return DCR_ERR_UNSUPPORTED;
-    *bytes = make_layout(M, N, true).bytes;
+    *bytes = make_layout(M, N).bytes;
     return DCR_OK;
 }
 
@@ -168,7 +169,7 @@ dcr_status dcr_cumulative_weights(const void* w, int64_t M, dcr_precision p, dou
     if (M < 1 || M > kMaxM || !w || !W || !ws) return DCR_ERR_INVALID_ARGUMENT;
     if (!valid_prec(p)) return DCR_ERR_UNSUPPORTED;
     if ((reinterpret_cast<uintptr_t>(ws) & 255u) != 0) return DCR_ERR_INVALID_ARGUMENT;
-    const Layout L = make_layout(M, 0, false);
+    const Layout L = make_layout(M, 0);
     if (ws_bytes < L.bytes) return DCR_ERR_WORKSPACE_TOO_SMALL;
     const WArgs wa = w_args(L, ws, M);
     ZArgs za{};
@@ -191,7 +192,7 @@ dcr_status dcr_sorted_uniforms(int64_t N, uint64_t seed, uint64_t stream_id, dcr
     if (!valid_prec(p)) return DCR_ERR_UNSUPPORTED;
     if (N == 0) return DCR_OK;
     if (!u || !ws || (reinterpret_cast<uintptr_t>(ws) & 255u) != 0) return DCR_ERR_INVALID_ARGUMENT;
-    const Layout L = make_layout(0, N, false);
+    const Layout L = make_layout(0, N);
     if (ws_bytes < L.bytes) return DCR_ERR_WORKSPACE_TOO_SMALL;
     WArgs wa{};
     const ZArgs za = z_args(L, ws, N, seed, stream_id);
@@ -226,14 +227,14 @@ dcr_status dcr_resample(const void* w, int64_t M, int64_t N, uint64_t seed, uint
     if (N > 0 && !r) return DCR_ERR_INVALID_ARGUMENT;
     if (!valid_prec(p)) return DCR_ERR_UNSUPPORTED;
     if ((reinterpret_cast<uintptr_t>(ws) & 255u) != 0) return DCR_ERR_INVALID_ARGUMENT;
-    const Layout L = make_layout(M, N, u_opt == nullptr);
+    const Layout L = make_layout(M, N);
     if (ws_bytes < L.bytes) return DCR_ERR_WORKSPACE_TOO_SMALL;
     const WArgs wa = w_args(L, ws, M);
     const ZArgs za = z_args(L, ws, N, seed, stream_id);
     const SharedArgs sh = shared_args(L, ws);
     const int prec = prec_code(p);
     const int vec = (aligned16(w) ? 1 : 0) | (aligned16(W_opt) ? 2 : 0);
-    double* u = u_opt ? u_opt : (N > 0 ? at<double>(ws, L.u_buf) : nullptr);
+    int32_t* wide = at<int32_t>(ws, L.wide);
     hipError_t e = timed(kKReduce, stream,
                          [&] { return dcr::launch_reduce(prec, w, wa, za, vec, stream); });
     if (dcr::finish_fits(wa, za)) {
@@ -250,15 +251,19 @@ dcr_status dcr_resample(const void* w, int64_t M, int64_t N, uint64_t seed, uint
     if (e == hipSuccess)
         e = timed(kKCarries, stream,
                   [&] { return dcr::launch_carries(wa, za, sh, dev_status, nullptr, stream); });
-    if (e == hipSuccess && N > 0)
-        e = timed(kKMatU, stream, [&] { return dcr::launch_materialize_u(za, sh, u, stream); });
     if (e == hipSuccess && W_opt)
         e = timed(kKMatW, stream,
                   [&] { return dcr::launch_materialize_w(prec, w, wa, sh, W_opt, vec, stream); });
-    if (e == hipSuccess && N > 0)
-        e = timed(kKMapFused, stream, [&] {
-            return dcr::launch_map_fused(prec, w, wa, sh, u, N, r, vec, stream);
-        });
+    if (e == hipSuccess && N > 0) {
+        if (dcr::map_is_dense(M, N))
+            e = timed(kKMapDense, stream, [&] {
+                return dcr::launch_map_dense(prec, w, wa, za, sh, u_opt, r, wide, vec, stream);
+            });
+        else
+            e = timed(kKMapFused, stream, [&] {
+                return dcr::launch_map_fused(prec, w, wa, za, sh, u_opt, r, vec, stream);
+            });
+    }
     return hip_status(e);
 }
 

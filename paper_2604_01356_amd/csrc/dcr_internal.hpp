@@ -45,6 +45,17 @@ hipError_t launch_reduce(int prec, const void* w, const WArgs& wa, const ZArgs& 
 constexpr int kFinishMaxZBlocks = 64;
 bool finish_fits(const WArgs& wa, const ZArgs& za);
 
+// N * kDenseRatio >= M: several uniforms per sub-tile on average, mapped by
+// the windowed linear merge (k_map_dense) instead of one search per uniform.
+constexpr int64_t kDenseRatio = 4;
+bool map_is_dense(int64_t M, int64_t N);
+int64_t dense_chunks(int64_t N);
+// Runs k_map_dense and then k_map_wide for the chunks it flags in `wide`
+// (dense_chunks(N) int32 flags, written before they are read).
+hipError_t launch_map_dense(int prec, const void* w, const WArgs& wa, const ZArgs& za,
+                            const SharedArgs& sh, double* u_out, int32_t* r, int32_t* wide,
+                            int vec_ok, hipStream_t s);
+
 hipError_t launch_carries(const WArgs& wa, const ZArgs& za, const SharedArgs& sh,
                           int32_t* dev_status, double* total_out, hipStream_t s);
 hipError_t launch_finish(int prec, const void* w, const WArgs& wa, const ZArgs& za,
@@ -53,8 +64,9 @@ hipError_t launch_finish(int prec, const void* w, const WArgs& wa, const ZArgs& 
 hipError_t launch_materialize_w(int prec, const void* w, const WArgs& wa, const SharedArgs& sh,
                                 double* W, int vec_ok, hipStream_t s);
 hipError_t launch_materialize_u(const ZArgs& za, const SharedArgs& sh, double* u, hipStream_t s);
-hipError_t launch_map_fused(int prec, const void* w, const WArgs& wa, const SharedArgs& sh,
-                            const double* u, int64_t N, int32_t* r, int vec_ok, hipStream_t s);
+hipError_t launch_map_fused(int prec, const void* w, const WArgs& wa, const ZArgs& za,
+                            const SharedArgs& sh, double* u_out, int32_t* r, int vec_ok,
+                            hipStream_t s);
 hipError_t launch_map_w(const double* W, int64_t M, const double* u, int64_t N, int32_t* r,
                         hipStream_t s);
 

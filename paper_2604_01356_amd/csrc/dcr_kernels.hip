@@ -405,6 +405,15 @@ __device__ __forceinline__ double uniform_of(double zrel, int64_t i, int64_t N, 
     return Z / ztot;
 }
 
+// Uniform i formed from the stored in-block spacing prefix and the scanned
+// spacing-block ends (the same values k_materialize_u writes).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double uniform_at(const ZArgs& za, double ztot, int64_t i) {
+    const int64_t g = i / kZBlock;
+    const double beta_g = (g == 0) ? 0.0 : za.beta[g - 1];
+    return uniform_of(za.zrel[i], i, za.N, beta_g, za.beta[g], ztot);
+}
+
 __device__ __forceinline__ void store_uniforms(double* __restrict__ u, int64_t i0, int nout,
                                                const double (&out)[kLane], int vec_out) {
     if (nout == kLane && vec_out) {
@@ -541,10 +550,16 @@ constexpr int kBetaLds = 4096;
 constexpr int kQuad = 4;
 constexpr int kUPerWG = kThreads / kQuad;
 
-template <typename Tin>
-__device__ void map_quad(const Tin* __restrict__ w, const WArgs& wa, const double* sbeta,
-                         int64_t kstride, int ns, double x, int64_t i, int qi,
-                         int32_t* __restrict__ r, int vec_ok) {
+// Location of the sub-tile that holds the first weight whose cumulative sum
+// reaches x (the block and sub-tile levels of the search), for one quad.
+struct SubtileLoc {
+    int64_t b, blk0, jlast;
+    int s, nsub;
+    double beta_b, beta_n, sigma;
+};
+
+__device__ SubtileLoc locate_subtile(const WArgs& wa, const double* sbeta, int64_t kstride,
+                                     int ns, double x, int qi) {
     const int64_t nb = wa.nb;
     // ---- block level: first b with beta_{b+1} >= x ----
     int qlo = 0, qhi = ns - 1;
@@ -564,14 +579,17 @@ __device__ void map_quad(const Tin* __restrict__ w, const WArgs& wa, const doubl
         else
             hi = mid;
     }
+    SubtileLoc L;
     const int64_t b = lo;
-    const double beta_b =
-        (b == 0) ? 0.0 : ((b % kstride == 0) ? sbeta[b / kstride - 1] : wa.beta[b - 1]);
-    const double beta_n = (kstride == 1) ? sbeta[b] : wa.beta[b];
-    const int64_t blk0 = b * kWBlock;
-    const int64_t blen = (wa.M - blk0 < kWBlock) ? wa.M - blk0 : kWBlock;
-    const int64_t jlast = blk0 + blen - 1;
+    L.b = b;
+    L.beta_b = (b == 0) ? 0.0 : ((b % kstride == 0) ? sbeta[b / kstride - 1] : wa.beta[b - 1]);
+    L.beta_n = (kstride == 1) ? sbeta[b] : wa.beta[b];
+    const double beta_b = L.beta_b, beta_n = L.beta_n;
+    L.blk0 = b * kWBlock;
+    const int64_t blen = (wa.M - L.blk0 < kWBlock) ? wa.M - L.blk0 : kWBlock;
+    L.jlast = L.blk0 + blen - 1;
     const int nsub = static_cast<int>((blen + kSub - 1) / kSub);
+    L.nsub = nsub;
     const double* se = wa.sub_end + b * kWSubPerBlock;
     // ---- sub-tile level: first s with end(s) >= x, where
     //      end(s) = min(beta_b + sigma_{s+1}, beta_{b+1}) and end(nsub-1) = beta_{b+1};
@@ -596,12 +614,24 @@ __device__ void map_quad(const Tin* __restrict__ w, const WArgs& wa, const doubl
     for (int k = 0; k < kPerLane; ++k)
         cnt += (s0 + k < nsub - 1 && fmin(beta_b + e[k], beta_n) < x) ? 1 : 0;
     const int s = quad_sum(cnt);
+    L.s = s;
     // sigma_s = stored end of sub-tile s-1, taken from the lane that read it
     double sig = 0.0;
 #pragma unroll
     for (int k = 0; k < kPerLane; ++k)
         if (s0 + k == s - 1) sig = e[k];
-    const double sigma = (s == 0) ? 0.0 : quad_bcast(sig, (s - 1) / kPerLane);
+    L.sigma = (s == 0) ? 0.0 : quad_bcast(sig, (s - 1) / kPerLane);
+    return L;
+}
+
+template <typename Tin>
+__device__ void map_quad(const Tin* __restrict__ w, const WArgs& wa, const double* sbeta,
+                         int64_t kstride, int ns, double x, int64_t i, int qi,
+                         int32_t* __restrict__ r, int vec_ok) {
+    const SubtileLoc loc = locate_subtile(wa, sbeta, kstride, ns, x, qi);
+    const int64_t blk0 = loc.blk0, jlast = loc.jlast;
+    const int s = loc.s, nsub = loc.nsub;
+    const double beta_b = loc.beta_b, beta_n = loc.beta_n, sigma = loc.sigma;
     const int64_t sub0 = blk0 + static_cast<int64_t>(s) * kSub;
     const int slen = static_cast<int>((jlast - sub0 + 1 < kSub) ? jlast - sub0 + 1 : kSub);
     const int nl = (slen + kLane - 1) / kLane;
@@ -691,10 +721,10 @@ __device__ void map_quad(const Tin* __restrict__ w, const WArgs& wa, const doubl
 
 // Map with the scanned block ends read from memory (after k_carries).
 template <typename Tin>
-__global__ __launch_bounds__(kThreads) void k_map_fused(const Tin* __restrict__ w, WArgs wa,
-                                                        SharedArgs sh, const double* __restrict__ u,
-                                                        int64_t N, int32_t* __restrict__ r,
-                                                        int vec_ok) {
+__global__ __launch_bounds__(kThreads) void k_map_fused(const Tin* __restrict__ w, WArgs wa, ZArgs za,
+                                                        SharedArgs sh, double* __restrict__ u_out,
+                                                        int32_t* __restrict__ r, int vec_ok) {
+    const int64_t N = za.N;
     __shared__ double sbeta[kBetaLds];
     const int t = threadIdx.x;
     const int64_t nb = wa.nb;
@@ -706,7 +736,12 @@ __global__ __launch_bounds__(kThreads) void k_map_fused(const Tin* __restrict__ 
     }
     const int64_t i = static_cast<int64_t>(blockIdx.x) * kUPerWG + (t / kQuad);
     const bool ok = sh.status[0] == kStatusOk;
-    const double x = (i < N && ok) ? threshold_for(u[i], sh.totals[0]) : 0.0;
+    double x = 0.0;
+    if (i < N) {
+        const double uu = uniform_at(za, sh.totals[1], i);
+        if (u_out && (t & (kQuad - 1)) == 0) u_out[i] = uu;
+        if (ok) x = threshold_for(uu, sh.totals[0]);
+    }
     lds_barrier();
     if (i >= N) return;   // the four lanes of a quad share i
     if (!ok) {
@@ -714,6 +749,200 @@ __global__ __launch_bounds__(kThreads) void k_map_fused(const Tin* __restrict__ 
         return;
     }
     map_quad<Tin>(w, wa, sbeta, kstride, ns, x, i, t & (kQuad - 1), r, vec_ok);
+}
+
+// ---------------------------------------------------------------------------
+// Inverse CMF in the dense regime (several uniforms per sub-tile: the
+// linear-merge limit of Alg. 5, where it behaves like Alg. 4).  A workgroup
+// takes 4096 consecutive uniforms; the first and the last are located by the
+// quad search, which bounds the sub-tiles all of them fall in (the split of
+// Alg. 5).  That span is re-summed, 16 sub-tiles (4096 weights) at a time,
+// and the merge of Alg. 4 is split by weights: each thread holds 16
+// consecutive normalised cumulative weights in registers (the values of
+// k_materialize_w), finds the run of the workgroup's sorted uniforms that falls
+// in its 16 bins by two searches of the uniforms in LDS, and places each of
+// them with 16 register comparisons.  A span wider than 64 sub-tiles is
+// flagged and left to k_map_wide (one quad search per uniform).
+// ---------------------------------------------------------------------------
+constexpr int kDenseU = 4096;
+constexpr int kDensePer = kDenseU / kThreads;
+constexpr int kWinSub = 16;
+constexpr int kMaxWin = 4;
+
+template <typename Tin>
+__global__ __launch_bounds__(kThreads) void k_map_dense(const Tin* __restrict__ w, WArgs wa, ZArgs za,
+                                                        SharedArgs sh, double* __restrict__ u_out,
+                                                        int32_t* __restrict__ r,
+                                                        int32_t* __restrict__ wide, int vec_ok) {
+    // block ends for the search of the span, then this workgroup's uniforms
+    __shared__ double lds[kBetaLds > kDenseU ? kBetaLds : kDenseU];
+    double* const sbeta = lds;
+    double* const su = lds;
+    __shared__ double uends[2];
+    __shared__ double ltot[kThreads];
+    __shared__ double wlast[kThreads];   // last normalised weight of each thread's 16
+    __shared__ int64_t span_ends[2];
+    const int t = threadIdx.x;
+    const int64_t N = za.N;
+    const int64_t nb = wa.nb;
+    const int64_t kstride = (nb + kBetaLds - 1) / kBetaLds;
+    const int ns = static_cast<int>((nb + kstride - 1) / kstride);
+    for (int q = t; q < ns; q += kThreads) {
+        const int64_t b = (static_cast<int64_t>(q) + 1) * kstride - 1;
+        sbeta[q] = wa.beta[b < nb ? b : nb - 1];
+    }
+    const int64_t c0 = static_cast<int64_t>(blockIdx.x) * kDenseU;
+    const int64_t c1 = (c0 + kDenseU < N) ? c0 + kDenseU : N;
+    const int nu = static_cast<int>(c1 - c0);
+    const bool ok = sh.status[0] == kStatusOk;
+    const double total = sh.totals[0];
+    const double ztot = sh.totals[1];
+    const int64_t iu0 = c0 + static_cast<int64_t>(t) * kDensePer;
+    const int nmine = clamp_count(c1 - iu0, kDensePer);
+    // this thread's 16 draws lie in one spacing block (16 divides 4096): load
+    // their in-block prefixes at once, then form the uniforms
+    double us[kDensePer];
+    if (nmine == kDensePer) {
+        const f64x2* q2 = reinterpret_cast<const f64x2*>(za.zrel + iu0);
+#pragma unroll
+        for (int v = 0; v < kDensePer / 2; ++v) {
+            const f64x2 d = q2[v];
+            us[2 * v] = d.x;
+            us[2 * v + 1] = d.y;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < kDensePer; ++q) us[q] = (q < nmine) ? za.zrel[iu0 + q] : 0.0;
+    }
+    const int64_t gz = iu0 / kZBlock;
+    const double zb = (gz == 0) ? 0.0 : za.beta[gz - 1];
+    const double zn = za.beta[gz < za.nb ? gz : za.nb - 1];
+#pragma unroll
+    for (int q = 0; q < kDensePer; ++q) us[q] = uniform_of(us[q], iu0 + q, N, zb, zn, ztot);
+    if (u_out) store_uniforms(u_out, iu0, nmine, us, (reinterpret_cast<uintptr_t>(u_out) & 15) == 0);
+    if (nmine > 0 && t * kDensePer == 0) uends[0] = us[0];
+#pragma unroll
+    for (int q = 0; q < kDensePer; ++q)
+        if (t * kDensePer + q == nu - 1) uends[1] = us[q];
+    lds_barrier();
+    if (!ok) {
+        for (int q = 0; q < nmine; ++q) r[iu0 + q] = -1;
+        if (t == 0) wide[blockIdx.x] = 0;
+        return;
+    }
+    // global sub-tile ids of the first and the last uniform (quads 0 and 1)
+    if (t < 2 * kQuad) {
+        const double xe = threshold_for(uends[(t < kQuad) ? 0 : 1], total);
+        const SubtileLoc loc = locate_subtile(wa, sbeta, kstride, ns, xe, t & (kQuad - 1));
+        if ((t & (kQuad - 1)) == 0) span_ends[t / kQuad] = loc.b * kWSubPerBlock + loc.s;
+    }
+    lds_barrier();
+    const int64_t gs0 = span_ends[0], gs1 = span_ends[1];
+    const bool is_wide = gs1 - gs0 + 1 > static_cast<int64_t>(kWinSub) * kMaxWin;
+    if (t == 0) wide[blockIdx.x] = is_wide ? 1 : 0;
+    if (is_wide) return;
+    // the block ends are no longer needed: the uniforms take their place
+#pragma unroll
+    for (int q = 0; q < kDensePer; ++q) su[t * kDensePer + q] = us[q];
+    const int row = t / kRowLanes;
+    const int lane = t % kRowLanes;
+    double wprev_window = -__builtin_huge_val();   // last weight before the current window
+    for (int64_t ws0 = gs0; ws0 <= gs1; ws0 += kWinSub) {
+        const int nw = static_cast<int>((gs1 - ws0 + 1 < kWinSub) ? gs1 - ws0 + 1 : kWinSub);
+        // re-sum the window: row r takes global sub-tile ws0 + r, so thread t
+        // holds the normalised cumulative weights of window entries 16t..16t+15
+        const int64_t gs = ws0 + row;
+        const int64_t b = gs / kWSubPerBlock;
+        const int sb = static_cast<int>(gs % kWSubPerBlock);
+        const int64_t blk0 = b * kWBlock;
+        const int64_t j0 = blk0 + static_cast<int64_t>(sb) * kSub + lane * kLane;
+        const int nv = (row < nw) ? clamp_count(wa.M - j0, kLane) : 0;
+        double xv[kLane];
+        load_chunk<Tin>(w + (nv > 0 ? j0 : 0), nv, (vec_ok & 1) != 0, xv);
+        double p[kLane];
+        p[0] = xv[0];
+#pragma unroll
+        for (int k = 1; k < kLane; ++k) p[k] = p[k - 1] + xv[k];
+        ltot[t] = p[kLane - 1];
+        lds_barrier();
+        double lv[kRowLanes];
+#pragma unroll
+        for (int k = 0; k < kRowLanes; ++k) lv[k] = ltot[row * kRowLanes + k];
+        double c = 0.0;
+#pragma unroll
+        for (int k = 0; k < kRowLanes; ++k)
+            if (k < lane) c = c + lv[k];
+        // normalised cumulative weights (the values of k_materialize_w);
+        // entries past the end of the weights read +inf
+        double wv[kLane];
+        if (nv > 0) {
+            const double sigma = (sb == 0) ? 0.0 : wa.sub_end[b * kWSubPerBlock + sb - 1];
+            const double beta_b = (b == 0) ? 0.0 : wa.beta[b - 1];
+            const double beta_n = wa.beta[b];
+            const int64_t jlast = ((blk0 + kWBlock < wa.M) ? blk0 + kWBlock : wa.M) - 1;
+#pragma unroll
+            for (int k = 0; k < kLane; ++k) {
+                const double S =
+                    (j0 + k == jlast) ? beta_n : fmin(beta_b + (sigma + (c + p[k])), beta_n);
+                wv[k] = (k < nv) ? S / total : __builtin_huge_val();
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < kLane; ++k) wv[k] = __builtin_huge_val();
+        }
+        wlast[t] = wv[kLane - 1];
+        lds_barrier();
+        // this thread's bins take the uniforms u with  lower < u <= upper;
+        // threads past the window's last sub-tile take none
+        const double lower = (t == 0) ? wprev_window : wlast[t - 1];
+        const double upper = wv[kLane - 1];
+        // first uniform > lower and first uniform > upper (searches over su)
+        int a = 0, e = 0;
+        if (row < nw) {
+#pragma unroll
+            for (int step = kDenseU; step >= 1; step >>= 1) {
+                if (a + step <= nu && su[a + step - 1] <= lower) a += step;
+                if (e + step <= nu && su[e + step - 1] <= upper) e += step;
+            }
+        }
+        const int64_t jbase = ws0 * kSub + static_cast<int64_t>(t) * kLane;
+        for (int iu = a; iu < e; ++iu) {
+            const double x = su[iu];
+            int cnt = 0;
+#pragma unroll
+            for (int k = 0; k < kLane; ++k) cnt += (wv[k] < x) ? 1 : 0;
+            r[c0 + iu] = static_cast<int32_t>(jbase + cnt);
+        }
+        wprev_window = wlast[nw * kRowLanes - 1];
+        lds_barrier();   // ltot / wlast are rewritten by the next window
+    }
+}
+
+// The flagged (wide-span) chunks of k_map_dense: one quad search per uniform.
+template <typename Tin>
+__global__ __launch_bounds__(kThreads) void k_map_wide(const Tin* __restrict__ w, WArgs wa, ZArgs za,
+                                                       SharedArgs sh, int32_t* __restrict__ r,
+                                                       const int32_t* __restrict__ wide,
+                                                       int vec_ok) {
+    __shared__ double sbeta[kBetaLds];
+    if (wide[blockIdx.x] == 0) return;   // workgroup-uniform
+    const int t = threadIdx.x;
+    const int64_t nb = wa.nb;
+    const int64_t kstride = (nb + kBetaLds - 1) / kBetaLds;
+    const int ns = static_cast<int>((nb + kstride - 1) / kstride);
+    for (int q = t; q < ns; q += kThreads) {
+        const int64_t b = (static_cast<int64_t>(q) + 1) * kstride - 1;
+        sbeta[q] = wa.beta[b < nb ? b : nb - 1];
+    }
+    lds_barrier();
+    const double total = sh.totals[0];
+    const double ztot = sh.totals[1];
+    const int64_t c0 = static_cast<int64_t>(blockIdx.x) * kDenseU;
+    const int64_t c1 = (c0 + kDenseU < za.N) ? c0 + kDenseU : za.N;
+    for (int64_t i = c0 + t / kQuad; i < c1; i += kUPerWG) {
+        const double x = threshold_for(uniform_at(za, ztot, i), total);
+        map_quad<Tin>(w, wa, sbeta, kstride, ns, x, i, t & (kQuad - 1), r, vec_ok);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -846,20 +1075,47 @@ hipError_t launch_materialize_u(const ZArgs& za, const SharedArgs& sh, double* u
     return hipGetLastError();
 }
 
-hipError_t launch_map_fused(int prec, const void* w, const WArgs& wa, const SharedArgs& sh,
-                            const double* u, int64_t N, int32_t* r, int vec_ok, hipStream_t s) {
-    if (N <= 0) return hipSuccess;
-    const int64_t grid = (N + kUPerWG - 1) / kUPerWG;
+hipError_t launch_map_fused(int prec, const void* w, const WArgs& wa, const ZArgs& za,
+                            const SharedArgs& sh, double* u_out, int32_t* r, int vec_ok,
+                            hipStream_t s) {
+    if (za.N <= 0) return hipSuccess;
+    const int64_t grid = (za.N + kUPerWG - 1) / kUPerWG;
     if (prec == kPrecFP32)
         hipLaunchKernelGGL(k_map_fused<float>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0,
-                           s, static_cast<const float*>(w), wa, sh, u, N, r, vec_ok);
+                           s, static_cast<const float*>(w), wa, za, sh, u_out, r, vec_ok);
     else
         hipLaunchKernelGGL(k_map_fused<double>, dim3(static_cast<unsigned>(grid)), dim3(kThreads),
-                           0, s, static_cast<const double*>(w), wa, sh, u, N, r, vec_ok);
+                           0, s, static_cast<const double*>(w), wa, za, sh, u_out, r, vec_ok);
     return hipGetLastError();
 }
 
+int64_t dense_chunks(int64_t N) { return (N + kDenseU - 1) / kDenseU; }
+
+hipError_t launch_map_dense(int prec, const void* w, const WArgs& wa, const ZArgs& za,
+                            const SharedArgs& sh, double* u_out, int32_t* r, int32_t* wide,
+                            int vec_ok, hipStream_t s) {
+    if (za.N <= 0) return hipSuccess;
+    const int64_t grid = dense_chunks(za.N);
+    if (prec == kPrecFP32)
+        hipLaunchKernelGGL(k_map_dense<float>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0,
+                           s, static_cast<const float*>(w), wa, za, sh, u_out, r, wide, vec_ok);
+    else
+        hipLaunchKernelGGL(k_map_dense<double>, dim3(static_cast<unsigned>(grid)), dim3(kThreads),
+                           0, s, static_cast<const double*>(w), wa, za, sh, u_out, r, wide, vec_ok);
+    if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+    if (prec == kPrecFP32)
+        hipLaunchKernelGGL(k_map_wide<float>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0,
+                           s, static_cast<const float*>(w), wa, za, sh, r, wide, vec_ok);
+    else
+        hipLaunchKernelGGL(k_map_wide<double>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0,
+                           s, static_cast<const double*>(w), wa, za, sh, r, wide, vec_ok);
+    return hipGetLastError();
+}
+
+bool map_is_dense(int64_t M, int64_t N) { return N * kDenseRatio >= M; }
+
 bool finish_fits(const WArgs& wa, const ZArgs& za) {
+    if (map_is_dense(wa.M, za.N)) return false;
     return za.N > 0 && wa.nb >= 1 && wa.nb <= kBetaLds && za.nb >= 1 && za.nb <= kFinishMaxZBlocks;
 }
 

@@ -144,6 +144,20 @@ def test_seed_and_stream_reproducible(dev, dcr):
     assert np.array_equal(a, b) and not np.array_equal(a, c)
 
 
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_dense_with_light_gap(dev, dcr, dtype):
+    """Dense overall (N > M/4) with a long run of negligible weights: the
+    workgroups whose uniforms straddle the run see a span of hundreds of
+    sub-tiles and take the per-uniform search."""
+    rng = np.random.default_rng(77)
+    M, N = 400000, 200000
+    w = np.exp(rng.normal(0, 1, M))
+    w[100000:300000] *= 1e-12
+    w = w.astype(dtype)
+    out = run_case(dcr, dev, w, N, seed=8, stream=0)
+    check_against_oracle(out, w, N, 8, 0, 1e-12 if dtype == np.float64 else DU_FP32, 2.0**-40)
+
+
 def test_many_blocks_sampled_index(dev, dcr):
     """More than 4096 weight blocks (M > 2^27): the map keeps every second block
     end in LDS and finishes the block search in memory."""
