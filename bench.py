@@ -29,7 +29,7 @@ W_BLOCK = 32768
 W_SUB = 256
 Z_BLOCK = 4096
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2604_01356_amd", "csrc", "dcr_kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_reduce.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 
 
 def reduce_bytes(M: int, N: int, s_w: int) -> int:
@@ -42,31 +42,207 @@ def reduce_bytes(M: int, N: int, s_w: int) -> int:
 
 def step_bytes(M: int, N: int, s_w: int, touched_sub: int) -> int:
     """Algorithmic bytes of one whole step (W and u not requested): the reduce
-    launch, the u write and read, the re-read of the touched sub-tiles and the
-    index write."""
-    return reduce_bytes(M, N, s_w) + 8 * N * 2 + 8 * (N + 1) + touched_sub * W_SUB * s_w + 4 * N
+    launch, the map's read of the in-block spacing prefixes, its re-read of the
+    weight sub-tiles that hold a draw, and the index write."""
+    return reduce_bytes(M, N, s_w) + 8 * N + touched_sub * W_SUB * s_w + 4 * N
 
 
-def source_digest() -> str:
+def map_bytes(N: int, s_w: int, touched_sub: int) -> int:
+    """Algorithmic HBM bytes of the map launch: the in-block spacing prefixes,
+    the weight sub-tiles that hold a draw (re-summed) and the index write."""
+    return 8 * N + touched_sub * W_SUB * s_w + 4 * N
+
+
+def source_digest(kernel: str) -> str:
+    """Digest of the source a kernel is built from: the device headers and the
+    kernel file up to the end of the kernel's own section (everything it can
+    use is defined above it), so later kernels do not change it."""
+    csrc = os.path.join(ROOT, "paper_2604_01356_amd", "csrc")
     h = hashlib.sha256()
-    for name in ("dcr_kernels.hip", "dcr_device.hpp"):
-        with open(os.path.join(ROOT, "paper_2604_01356_amd", "csrc", name), "rb") as f:
+    for name in ("dcr_device.hpp", "dcr_internal.hpp"):
+        with open(os.path.join(csrc, name), "rb") as f:
             h.update(f.read())
+    with open(KERNEL_SOURCE, "r") as f:
+        text = f.read()
+    start = text.index(f"void {kernel}(")
+    end = text.find("\n// ----", start)
+    h.update(text[: end if end >= 0 else len(text)].encode())
     return h.hexdigest()[:16]
 
 
-def load_traffic(workload: str, precision: str):
-    """HBM traffic of k_reduce from committed rocprofv3 counter runs, or None
-    if absent or taken on a different kernel source."""
+def load_traffic(workload: str, precision: str, kernel: str):
+    """HBM bytes per launch of `kernel` from committed rocprofv3 counter runs,
+    or None if absent or taken on a different kernel source."""
     try:
         with open(TRAFFIC_FILE) as f:
             d = json.load(f)
     except (OSError, ValueError):
         return None
-    e = d.get(f"{workload}/{precision}")
-    if not e or e.get("source_digest") != source_digest():
+    e = d.get(f"{workload}/{precision}/{kernel}")
+    if not e or e.get("source_digest") != source_digest(KERNEL_NAMES[kernel]):
         return None
     return e.get("bytes_per_launch")
+
+
+# rocprofv3 kernel-name fragment of each timed launch kind
+KERNEL_NAMES = {"reduce": "k_reduce", "finish": "k_finish", "map_dense": "k_map_dense",
+                "map_fused": "k_map_fused", "carries": "k_carries"}
+COPY_KERNEL = "neg_kernel"
+
+
+def _counter_rows(path: str):
+    import csv
+    with open(path, newline="") as f:
+        for row in csv.DictReader(f):
+            yield row["Kernel_Name"], row["Counter_Name"], float(row["Counter_Value"])
+
+
+def _mean_per_dispatch(path: str, counter: str, name_part: str) -> float:
+    vals = [v for k, c, v in _counter_rows(path) if c == counter and name_part in k]
+    if not vals:
+        raise SystemExit(f"{path}: no {counter} rows for a kernel named like {name_part}")
+    return sum(vals) / len(vals)
+
+
+def write_traffic(args):
+    """Turn four rocprofv3 --pmc CSV files (FETCH_SIZE and WRITE_SIZE of the
+    bench command and of the copy calibration) into bytes per launch, each
+    counter scaled by what it reads for the copy of known size."""
+    fetch, write, cfetch, cwrite = args.write_traffic
+    copy_kib = CALIBRATE_BYTES / 1024.0
+    f_scale = copy_kib / _mean_per_dispatch(cfetch, "FETCH_SIZE", COPY_KERNEL)
+    w_scale = copy_kib / _mean_per_dispatch(cwrite, "WRITE_SIZE", COPY_KERNEL)
+    kname = KERNEL_NAMES[args.traffic_kernel]
+    fk = _mean_per_dispatch(fetch, "FETCH_SIZE", kname) * f_scale
+    wk = _mean_per_dispatch(write, "WRITE_SIZE", kname) * w_scale
+    try:
+        with open(TRAFFIC_FILE) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        d = {}
+    d[f"{args.workload}/{args.precision}/{args.traffic_kernel}"] = {
+        "bytes_per_launch": (fk + wk) * 1024.0,
+        "fetch_kib_per_launch": fk,
+        "write_kib_per_launch": wk,
+        "copy_scale_fetch": f_scale,
+        "copy_scale_write": w_scale,
+        "source_digest": source_digest(kname),
+        "counter_files": [os.path.basename(x) for x in args.write_traffic],
+    }
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(d, f, indent=1, sort_keys=True)
+        f.write("\n")
+    print(json.dumps(d[f"{args.workload}/{args.precision}/{args.traffic_kernel}"]))
+
+
+CALIBRATE_BYTES = 1 << 30
+
+
+def calibrate_copy():
+    """A plain streaming copy of known size (1 GiB read, 1 GiB written) for
+    scaling the HBM byte counters."""
+    import torch
+    n = CALIBRATE_BYTES // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "neg copy", "bytes_read": CALIBRATE_BYTES,
+                      "bytes_written": CALIBRATE_BYTES}), flush=True)
+
+
+def batched_reduce_bytes(w_off, n_off, s_w: int) -> int:
+    """Algorithmic HBM bytes of the batched reduce launch: every filter's
+    weights once, its sub-tile ends and block totals, its N_b + 1 spacing
+    prefixes and block totals."""
+    import numpy as np
+    Mb = np.diff(w_off)
+    Nb = np.diff(n_off)
+    nwb = int(np.sum(-(-Mb // W_BLOCK)))
+    nzb = int(np.sum(np.where(Nb > 0, -(-(Nb + 1) // Z_BLOCK), 0)))
+    return int(Mb.sum()) * s_w + nwb * ((W_BLOCK // W_SUB) * 8 + 8) + int((Nb + 1).sum()) * 8 \
+        + nzb * 8
+
+
+def measure_batched(dcr, torch, dev, steps: int, warmup: int, cpu_seconds: float):
+    """The 4096-filter workload in the binary32 form, one dcr_resample_batched
+    call per step (the weights, 2.4 GB, exceed the Infinity Cache)."""
+    import numpy as np
+
+    import workloads
+    bw = workloads.batched()
+    w32 = bw.w32
+    sumN = int(bw.n_off[-1])
+    w = torch.from_numpy(w32).to(dev)
+    w_off = torch.from_numpy(bw.w_off).to(dev)
+    n_off = torch.from_numpy(bw.n_off).to(dev)
+    r = torch.empty(sumN, dtype=torch.int32, device=dev)
+    st = torch.empty(1, dtype=torch.int32, device=dev)
+    ws = torch.empty(dcr.dcr_batched_workspace_bytes(bw.B, w32.size, sumN, dcr.DCR_FP32_COMP),
+                     dtype=torch.uint8, device=dev)
+
+    def step(k):
+        dcr.dcr_resample_batched(w, w_off, n_off, seed=k, r=r, dev_status=st, ws=ws)
+
+    for k in range(warmup):
+        step(k)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for k in range(steps):
+        step(k)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    dcr.dcr_profile_begin(steps * 8)
+    for k in range(steps):
+        step(k)
+    prof = dcr.dcr_profile_end()
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    kernels = {k: v[1] / v[0] for k, v in prof.items() if v[0] > 0}
+    step(0)
+    r0 = r.cpu().numpy()
+    red_bytes = batched_reduce_bytes(bw.w_off, bw.n_off, 4)
+    achieved = red_bytes / (kernels["batch_reduce"] * 1e-3) / 1e9
+    out = {
+        "workload": bw.description,
+        "B": bw.B, "sum_M": int(w32.size), "sum_N": sumN,
+        "ms_per_step": ms,
+        "value": sumN / (ms * 1e-3),
+        "unit": "particles/s",
+        "weights_per_s": w32.size / (ms * 1e-3),
+        "step_weight_gbs": w32.nbytes / (ms * 1e-3) / 1e9,
+        "kernels_ms": kernels,
+        "roofline": {"kernel": "k_reduce_batched", "bound": "hbm", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "algorithmic_bytes": red_bytes,
+                     "avg_launch_us": kernels["batch_reduce"] * 1e3},
+    }
+    if cpu_seconds > 0:
+        import oracle
+        # the oracle on a bounded sample: the first filters until the time is spent
+        t0 = time.perf_counter()
+        done_n = 0
+        mism = 0
+        b = 0
+        while b < bw.B and time.perf_counter() - t0 < cpu_seconds:
+            a, e = bw.w_off[b], bw.w_off[b + 1]
+            Nb = int(bw.n_off[b + 1] - bw.n_off[b])
+            rb = oracle.resample(w32[a:e], Nb, seed=0, stream=b)[0]
+            mism += int(np.sum(rb != r0[bw.n_off[b]:bw.n_off[b + 1]]))
+            done_n += Nb
+            b += 1
+        t = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": done_n / t, "unit": "particles/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"oracle on filters 0..{b - 1} of the batch "
+                                         f"({done_n} draws) in {t:.1f} s, single thread"}
+        out["mismatches_vs_oracle_sample"] = mism
+    del w, ws, r
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(wl, w_host, seconds: float):
@@ -101,11 +277,21 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="sparse", choices=["sparse", "equal", "engmf", "single"])
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 4096-filter batched workload reported beside the main line")
     ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
     ap.add_argument("--no-compare", action="store_true", help="skip the other precision")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only the copy of known size used to scale HBM counters")
+    ap.add_argument("--write-traffic", nargs=4, metavar="CSV",
+                    help="FETCH_SIZE, WRITE_SIZE csv of this command, then of --calibrate-copy")
+    ap.add_argument("--traffic-kernel", default="reduce", choices=sorted(KERNEL_NAMES))
     args = ap.parse_args()
+    if args.write_traffic:
+        write_traffic(args)
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -122,6 +308,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no GPU", file=sys.stderr)
         sys.exit(1)
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     dev = torch.device("cuda:0")
     dcr.library()
     wl = workloads.CONFIGS[args.workload]()
@@ -159,22 +348,38 @@ def main():
         torch.cuda.synchronize()
         assert int(st.item()) == 0
         kernels = {k: v[1] / v[0] for k, v in prof.items() if v[0] > 0}
-        # one more step with seed 0 for the parity spot check
-        step(0)
+        # one more step with seed 0 for the parity spot check, with W
+        W0 = None
+        if want_w:
+            W_dev = torch.empty(wl.M, dtype=torch.float64, device=dev)
+            dcr.dcr_resample(ws_copies[0], wl.N, seed=0, stream_id=0, r=r, W_out=W_dev,
+                             dev_status=st, ws=ws)
+            W0 = W_dev.cpu().numpy()
+            del W_dev
+        else:
+            step(0)
         r0 = r[: wl.N].cpu().numpy().copy()
         for t in ws_copies:
             del t
         del ws_copies
         torch.cuda.empty_cache()
-        return ms_step, kernels, r0, w_host
+        return ms_step, kernels, r0, w_host, W0
 
-    ms, kernels, r_gpu, w_host = measure(args.precision, args.steps, args.warmup)
+    want_w = not args.no_cpu and args.precision == "f32"
+    ms, kernels, r_gpu, w_host, W_gpu = measure(args.precision, args.steps, args.warmup)
+    want_w = False
     s_w = 4 if args.precision == "f32" else 8
     touched = int(len(np.unique(r_gpu // W_SUB)))
-    red_ms = kernels.get("reduce", float("nan"))
-    red_bytes = reduce_bytes(wl.M, wl.N, s_w)
-    achieved = red_bytes / (red_ms * 1e-3) / 1e9
-    traffic = load_traffic(args.workload, args.precision)
+    # the dominant launch kind of the step and its algorithmic bytes
+    dom = max(kernels, key=kernels.get)
+    if dom == "reduce":
+        dom_bytes = reduce_bytes(wl.M, wl.N, s_w)
+    elif dom in ("finish", "map_dense", "map_fused"):
+        dom_bytes = map_bytes(wl.N, s_w, touched)
+    else:
+        raise SystemExit(f"bench.py: no byte model for the launch kind {dom}")
+    achieved = dom_bytes / (kernels[dom] * 1e-3) / 1e9
+    traffic = load_traffic(args.workload, args.precision, dom)
     out = {
         "metric": METRIC,
         "value": wl.N / (ms * 1e-3),
@@ -200,19 +405,20 @@ def main():
         "step_hbm_frac": step_bytes(wl.M, wl.N, s_w, touched) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "kernels_ms": kernels,
         "roofline": {
-            "kernel": "k_reduce",
+            "kernel": KERNEL_NAMES[dom],
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "algorithmic_bytes": red_bytes,
+            "algorithmic_bytes": dom_bytes,
+            "avg_launch_us": kernels[dom] * 1e3,
         },
     }
     if not args.no_compare:
         other = "f64" if args.precision == "f32" else "f32"
-        ms_o, kern_o, _, _ = measure(other, max(5, args.steps // 2), 2)
+        ms_o, kern_o, _, _, _ = measure(other, max(5, args.steps // 2), 2)
         out[f"compare_{other}"] = {
             "ms_per_step": ms_o,
             "value": wl.N / (ms_o * 1e-3),
@@ -223,6 +429,19 @@ def main():
         cb, r_or = cpu_baseline(wl, w_host, args.cpu_seconds)
         out["cpu_baseline"] = cb
         out["mismatches_vs_oracle_seed0"] = int(np.sum(r_gpu != r_or))
+        if W_gpu is not None:
+            # the binary32-input result against the oracle on the binary64 weights
+            import oracle
+            r64, W64, _ = oracle.resample(wl.w64, wl.N, seed=0, stream=0)
+            out["fp32_vs_fp64"] = {
+                "max_abs_dW": float(np.max(np.abs(W_gpu - W64))),
+                "mismatches": int(np.sum(r_gpu != r64)),
+                "mismatch_rate": float(np.mean(r_gpu != r64)),
+                "reference": "oracle on the binary64 weights, seed 0",
+            }
+    if not args.no_batched:
+        out["batched"] = measure_batched(dcr, torch, dev, max(5, args.steps // 5), 2,
+                                         0.0 if args.no_cpu else args.cpu_seconds / 2)
     print(json.dumps(out), flush=True)
 
 

@@ -113,11 +113,52 @@ dcr_status dcr_resample(const void* w, int64_t M, int64_t N, uint64_t seed, uint
                         dcr_precision p, int32_t* r, double* W_opt, double* u_opt,
                         int32_t* dev_status, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* Batched form: B independent filters in one call (one filter = one
+ * single-distribution problem of Sec. I-III, Alg. 5 on its own weights).
+ * Filter b owns weights w[w_off[b] .. w_off[b+1]) and draws
+ * r[n_off[b] .. n_off[b+1]); it uses Philox stream id b, so its indices equal
+ * those of dcr_resample(w + w_off[b], M_b, N_b, seed, b, p, ...) bit for bit.
+ *
+ * dcr_batched_workspace_bytes: workspace for up to B filters with at most
+ * sumM_max weights and sumN_max draws in total.  Host only.
+ *   Errors: DCR_ERR_INVALID_ARGUMENT for B < 1, B > 2^24, sumM_max < B,
+ *   sumM_max or sumN_max above 2^40 or negative, bytes == NULL;
+ *   DCR_ERR_UNSUPPORTED for an unknown precision. */
+dcr_status dcr_batched_workspace_bytes(int32_t B, int64_t sumM_max, int64_t sumN_max,
+                                       dcr_precision p, size_t* bytes);
+
+/* dcr_resample_batched:
+ *   w        concatenated weights, binary64 or binary32 as p says; a filter
+ *            may start at any element (no alignment needed).
+ *   w_off    [B+1] int64 DEVICE array, non-decreasing, w_off[0] == 0,
+ *            1 <= M_b = w_off[b+1] - w_off[b] <= 2^31 - 1, w_off[B] <= sumM_max.
+ *   n_off    [B+1] int64 DEVICE array, n_off[0] == 0,
+ *            0 <= N_b = n_off[b+1] - n_off[b] <= 2^31 - 2, n_off[B] <= sumN_max.
+ *   r        [n_off[B]] int32 out: indices local to each filter (0..M_b-1),
+ *            non-decreasing within a filter.
+ *   seg_status [B] int32 out or NULL: DCR_OK or DCR_ERR_BAD_WEIGHTS per filter
+ *            (a bad filter's indices are -1; the others are unaffected).
+ *   dev_status [1] int32 out or NULL: DCR_OK; DCR_ERR_BAD_WEIGHTS if any filter
+ *            is bad; DCR_ERR_INVALID_ARGUMENT if the offsets break the rules
+ *            above; DCR_ERR_CAPACITY_EXCEEDED if the totals exceed sumM_max /
+ *            sumN_max.  In the last two cases nothing else is written.
+ *   ws       workspace of dcr_batched_workspace_bytes(B, sumM_max, sumN_max, p)
+ *            bytes, 256-byte aligned.
+ * The offsets are read on the device, so the call never synchronises with the
+ * host.  Host-visible errors are those of dcr_batched_workspace_bytes, NULL
+ * pointers, a misaligned or small workspace. */
+dcr_status dcr_resample_batched(const void* w, const int64_t* w_off, const int64_t* n_off,
+                                int32_t B, int64_t sumM_max, int64_t sumN_max, uint64_t seed,
+                                dcr_precision p, int32_t* r, int32_t* seg_status,
+                                int32_t* dev_status, void* ws, size_t ws_bytes,
+                                hipStream_t stream);
+
 /* Kernel timing for measurement (not part of the sampling contract).
- * dcr_profile_begin(cap) creates HIP events for up to `cap` kernel launches
- * and makes every later call record an event pair around each kernel it
- * enqueues.  dcr_profile_end() synchronises on the last event, stops
- * recording and, for each kernel kind k (see dcr_profile_kind_name), stores
+ * dcr_profile_begin(cap) creates HIP events for up to `cap` kernel launches;
+ * every later launch records its own start and end into the next pair
+ * (hipExtLaunchKernel), so an interval covers the kernel alone.
+ * dcr_profile_end() waits for the device, stops recording and, for each
+ * kernel kind k (see dcr_profile_kind_name), stores
  * the launch count in counts[k] and the summed milliseconds in ms[k]
  * (arrays of n_kinds entries, host memory).  Kinds beyond n_kinds are dropped.
  * Not thread safe; meant for one measuring thread. */

@@ -10,11 +10,13 @@ from ._binding import (  # noqa: F401
     DCR_FP32_COMP,
     DCR_FP64,
     DcrError,
+    dcr_batched_workspace_bytes,
     dcr_cumulative_weights,
     dcr_inverse_cmf,
     dcr_profile_begin,
     dcr_profile_end,
     dcr_resample,
+    dcr_resample_batched,
     dcr_sorted_uniforms,
     dcr_status_string,
     dcr_workspace_bytes,

@@ -61,6 +61,11 @@ def library():
     lib.dcr_inverse_cmf.restype = ctypes.c_int
     lib.dcr_resample.argtypes = [P, i64, i64, u64, u64, ctypes.c_int, P, P, P, P, P, sz, P]
     lib.dcr_resample.restype = ctypes.c_int
+    lib.dcr_batched_workspace_bytes.argtypes = [i32, i64, i64, ctypes.c_int, ctypes.POINTER(sz)]
+    lib.dcr_batched_workspace_bytes.restype = ctypes.c_int
+    lib.dcr_resample_batched.argtypes = [P, P, P, i32, i64, i64, u64, ctypes.c_int, P, P, P, P,
+                                         sz, P]
+    lib.dcr_resample_batched.restype = ctypes.c_int
     lib.dcr_profile_begin.argtypes = [i32]
     lib.dcr_profile_begin.restype = ctypes.c_int
     lib.dcr_profile_end.argtypes = [i32, P, P]
@@ -201,6 +206,47 @@ def dcr_resample(w, N: int, seed: int, stream_id: int = 0, r=None, W_out=None, u
         _ptr(w), M, N, int(seed), int(stream_id), p, _ptr(r), _ptr(W_out), _ptr(u_out),
         _ptr(dev_status), _ptr(ws), ws.numel(), _stream(w.device)))
     return r[:N]
+
+
+def dcr_batched_workspace_bytes(B: int, sumM_max: int, sumN_max: int,
+                                precision: int = DCR_FP64) -> int:
+    out = ctypes.c_size_t(0)
+    _check("dcr_batched_workspace_bytes", library().dcr_batched_workspace_bytes(
+        int(B), int(sumM_max), int(sumN_max), int(precision), ctypes.byref(out)))
+    return int(out.value)
+
+
+def dcr_resample_batched(w, w_off, n_off, seed: int, sumM_max: int | None = None,
+                         sumN_max: int | None = None, r=None, seg_status=None, dev_status=None,
+                         ws=None):
+    """B filters in one call; w_off / n_off are int64 device tensors of B+1
+    offsets.  sumM_max / sumN_max bound the totals (default: the size of w and
+    of r).  Returns r (indices local to each filter)."""
+    import torch
+    _dev_tensor(w, "w")
+    _dev_tensor(w_off, "w_off", torch.int64)
+    _dev_tensor(n_off, "n_off", torch.int64)
+    B = w_off.numel() - 1
+    if n_off.numel() != B + 1:
+        raise ValueError("w_off and n_off must have the same length")
+    p = precision_of(w)
+    sumM = int(w.numel() if sumM_max is None else sumM_max)
+    if r is None:
+        if sumN_max is None:
+            raise ValueError("give r or sumN_max")
+        r = torch.empty(max(int(sumN_max), 1), dtype=torch.int32, device=w.device)
+    sumN = int(r.numel() if sumN_max is None else sumN_max)
+    _dev_tensor(r, "r", torch.int32, sumN)
+    _dev_tensor(seg_status, "seg_status", torch.int32, B)
+    _dev_tensor(dev_status, "dev_status", torch.int32, 1)
+    need = dcr_batched_workspace_bytes(B, sumM, sumN, p)
+    if ws is None:
+        ws = torch.empty(need, dtype=torch.uint8, device=w.device)
+    _dev_tensor(ws, "ws")
+    _check("dcr_resample_batched", library().dcr_resample_batched(
+        _ptr(w), _ptr(w_off), _ptr(n_off), B, sumM, sumN, int(seed), p, _ptr(r),
+        _ptr(seg_status), _ptr(dev_status), _ptr(ws), ws.numel(), _stream(w.device)))
+    return r
 
 
 def dcr_profile_begin(cap: int):

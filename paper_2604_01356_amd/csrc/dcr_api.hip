@@ -9,6 +9,10 @@
 #include "dcr.h"
 #include "dcr_internal.hpp"
 
+namespace dcr {
+LaunchEvents g_launch_events;
+}
+
 namespace {
 
 using dcr::SharedArgs;
@@ -107,10 +111,13 @@ SharedArgs shared_args(const Layout& L, void* ws) {
 // Optional kernel timing (dcr_profile_*).
 // ---------------------------------------------------------------------------
 enum Kind {
-    kKReduce = 0, kKCarries, kKMatW, kKMatU, kKMapFused, kKMapW, kKFinish, kKMapDense, kNumKinds
+    kKReduce = 0, kKCarries, kKMatW, kKMatU, kKMapFused, kKMapW, kKFinish, kKMapDense, kKMapWide,
+    kKBatchPlan, kKBatchReduce, kKBatchCarries, kKBatchMap, kNumKinds
 };
 const char* const kKindNames[kNumKinds] = {"reduce",   "carries", "materialize_w", "materialize_u",
-                                           "map_fused", "map_w",  "finish",        "map_dense"};
+                                           "map_fused", "map_w",  "finish",        "map_dense",
+                                           "map_wide",  "batch_plan", "batch_reduce",
+                                           "batch_carries", "batch_map"};
 
 struct Profiler {
     bool on = false;
@@ -121,17 +128,23 @@ struct Profiler {
 };
 Profiler g_prof;
 
+// Runs one launcher; while profiling, its kernel records its own start and
+// end into the next pair of events (a launcher that launches nothing, e.g. for
+// N = 0, uses no slot).
 template <class F>
 hipError_t timed(int kind, hipStream_t s, F&& launch) {
-    int slot = -1;
-    if (g_prof.on && g_prof.used < g_prof.cap) {
-        slot = g_prof.used++;
-        (void)hipEventRecord(g_prof.ev[2 * slot], s);
-    }
+    (void)s;
+    if (!g_prof.on || g_prof.used >= g_prof.cap) return launch();
+    const int slot = g_prof.used;
+    dcr::g_launch_events.start = g_prof.ev[2 * slot];
+    dcr::g_launch_events.stop = g_prof.ev[2 * slot + 1];
+    const int64_t before = dcr::g_launch_events.launches;
     const hipError_t e = launch();
-    if (slot >= 0) {
-        (void)hipEventRecord(g_prof.ev[2 * slot + 1], s);
+    dcr::g_launch_events.start = nullptr;
+    dcr::g_launch_events.stop = nullptr;
+    if (dcr::g_launch_events.launches != before) {
         g_prof.kind[slot] = kind;
+        ++g_prof.used;
     }
     return e;
 }
@@ -255,15 +268,124 @@ dcr_status dcr_resample(const void* w, int64_t M, int64_t N, uint64_t seed, uint
         e = timed(kKMatW, stream,
                   [&] { return dcr::launch_materialize_w(prec, w, wa, sh, W_opt, vec, stream); });
     if (e == hipSuccess && N > 0) {
-        if (dcr::map_is_dense(M, N))
+        if (dcr::map_is_dense(M, N)) {
             e = timed(kKMapDense, stream, [&] {
                 return dcr::launch_map_dense(prec, w, wa, za, sh, u_opt, r, wide, vec, stream);
             });
-        else
+            if (e == hipSuccess)
+                e = timed(kKMapWide, stream, [&] {
+                    return dcr::launch_map_wide(prec, w, wa, za, sh, r, wide, vec, stream);
+                });
+        } else
             e = timed(kKMapFused, stream, [&] {
                 return dcr::launch_map_fused(prec, w, wa, za, sh, u_opt, r, vec, stream);
             });
     }
+    return hip_status(e);
+}
+
+// ---------------------------------------------------------------------------
+// Batched form
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int64_t kMaxBatch = 1 << 24;
+constexpr int64_t kMaxSum = 1LL << 40;
+
+struct BatchLayout {
+    int64_t wt_cap = 0, zt_cap = 0, mc_cap = 0;
+    size_t head = 0, wt_base = 0, zt_base = 0, mc_base = 0, seg_status = 0, seg_totals = 0;
+    size_t wt_tot = 0, wt_beta = 0, wt_sub = 0, zt_tot = 0, zt_beta = 0, zrel = 0;
+    size_t bytes = 0;
+};
+
+BatchLayout make_batch_layout(int64_t B, int64_t sumM, int64_t sumN) {
+    BatchLayout L;
+    L.wt_cap = (sumM + dcr::kBatchWBlock - 1) / dcr::kBatchWBlock + B;
+    L.zt_cap = (sumN + B + dcr::kBatchZBlock - 1) / dcr::kBatchZBlock + B;
+    L.mc_cap = (sumN + dcr::kBatchChunk - 1) / dcr::kBatchChunk + B;
+    size_t off = 0;
+    auto take = [&](size_t n) {
+        const size_t at_ = off;
+        off = align256(off + n);
+        return at_;
+    };
+    L.head = take(256);
+    L.wt_base = take(sizeof(int64_t) * (B + 1));
+    L.zt_base = take(sizeof(int64_t) * (B + 1));
+    L.mc_base = take(sizeof(int64_t) * (B + 1));
+    L.seg_status = take(sizeof(int32_t) * B);
+    L.seg_totals = take(sizeof(double) * 2 * B);
+    L.wt_tot = take(sizeof(double) * L.wt_cap);
+    L.wt_beta = take(sizeof(double) * L.wt_cap);
+    L.wt_sub = take(sizeof(double) * L.wt_cap * kWSubPerBlock);
+    L.zt_tot = take(sizeof(double) * L.zt_cap);
+    L.zt_beta = take(sizeof(double) * L.zt_cap);
+    L.zrel = take(sizeof(double) * (sumN + B));
+    L.bytes = off;
+    return L;
+}
+
+bool batch_sizes_ok(int64_t B, int64_t sumM, int64_t sumN) {
+    if (B < 1 || B > kMaxBatch || sumM < B || sumM > kMaxSum || sumN < 0 || sumN > kMaxSum)
+        return false;
+    const BatchLayout L = make_batch_layout(B, sumM, sumN);
+    return L.wt_cap + L.zt_cap <= 0x7FFFFFFF && L.mc_cap <= 0x7FFFFFFF;
+}
+
+}  // namespace
+
+dcr_status dcr_batched_workspace_bytes(int32_t B, int64_t sumM_max, int64_t sumN_max,
+                                       dcr_precision p, size_t* bytes) {
+    if (!bytes || !batch_sizes_ok(B, sumM_max, sumN_max)) return DCR_ERR_INVALID_ARGUMENT;
+    if (!valid_prec(p)) return DCR_ERR_UNSUPPORTED;
+    *bytes = make_batch_layout(B, sumM_max, sumN_max).bytes;
+    return DCR_OK;
+}
+
+dcr_status dcr_resample_batched(const void* w, const int64_t* w_off, const int64_t* n_off,
+                                int32_t B, int64_t sumM_max, int64_t sumN_max, uint64_t seed,
+                                dcr_precision p, int32_t* r, int32_t* seg_status,
+                                int32_t* dev_status, void* ws, size_t ws_bytes,
+                                hipStream_t stream) {
+    if (!batch_sizes_ok(B, sumM_max, sumN_max)) return DCR_ERR_INVALID_ARGUMENT;
+    if (!w || !w_off || !n_off || !ws || (sumN_max > 0 && !r)) return DCR_ERR_INVALID_ARGUMENT;
+    if (!valid_prec(p)) return DCR_ERR_UNSUPPORTED;
+    if ((reinterpret_cast<uintptr_t>(ws) & 255u) != 0) return DCR_ERR_INVALID_ARGUMENT;
+    const BatchLayout L = make_batch_layout(B, sumM_max, sumN_max);
+    if (ws_bytes < L.bytes) return DCR_ERR_WORKSPACE_TOO_SMALL;
+    dcr::BatchArgs ba{};
+    ba.w_off = w_off;
+    ba.n_off = n_off;
+    ba.B = B;
+    ba.seed = seed;
+    ba.wt_cap = L.wt_cap;
+    ba.zt_cap = L.zt_cap;
+    ba.mc_cap = L.mc_cap;
+    ba.sumM_cap = sumM_max;
+    ba.sumN_cap = sumN_max;
+    ba.wt_base = at<int64_t>(ws, L.wt_base);
+    ba.zt_base = at<int64_t>(ws, L.zt_base);
+    ba.mc_base = at<int64_t>(ws, L.mc_base);
+    ba.head = at<int32_t>(ws, L.head);
+    ba.wt_tot = at<double>(ws, L.wt_tot);
+    ba.wt_beta = at<double>(ws, L.wt_beta);
+    ba.wt_sub = at<double>(ws, L.wt_sub);
+    ba.zt_tot = at<double>(ws, L.zt_tot);
+    ba.zt_beta = at<double>(ws, L.zt_beta);
+    ba.zrel = at<double>(ws, L.zrel);
+    ba.seg_status = seg_status ? seg_status : at<int32_t>(ws, L.seg_status);
+    ba.seg_totals = at<double>(ws, L.seg_totals);
+    const int prec = prec_code(p);
+    hipError_t e = timed(kKBatchPlan, stream, [&] { return dcr::launch_batch_plan(ba, dev_status, stream); });
+    if (e == hipSuccess)
+        e = timed(kKBatchReduce, stream,
+                  [&] { return dcr::launch_reduce_batched(prec, w, ba, stream); });
+    if (e == hipSuccess)
+        e = timed(kKBatchCarries, stream, [&] { return dcr::launch_carries_batched(ba, stream); });
+    if (e == hipSuccess)
+        e = timed(kKBatchMap, stream,
+                  [&] { return dcr::launch_map_batched(prec, w, ba, r, dev_status, stream); });
     return hip_status(e);
 }
 
@@ -272,7 +394,8 @@ dcr_status dcr_profile_begin(int32_t cap) {
     g_prof.ev.assign(2 * static_cast<size_t>(cap), nullptr);
     g_prof.kind.assign(cap, -1);
     for (auto& ev : g_prof.ev)
-        if (hipEventCreate(&ev) != hipSuccess) return DCR_ERR_HIP;
+        if (hipEventCreateWithFlags(&ev, hipEventDisableSystemFence) != hipSuccess)
+            return DCR_ERR_HIP;
     g_prof.cap = cap;
     g_prof.used = 0;
     g_prof.on = true;
@@ -287,8 +410,8 @@ dcr_status dcr_profile_end(int32_t n_kinds, int64_t* counts, double* ms) {
         if (counts) counts[k] = 0;
         if (ms) ms[k] = 0.0;
     }
-    if (g_prof.used > 0 && hipEventSynchronize(g_prof.ev[2 * g_prof.used - 1]) != hipSuccess)
-        st = DCR_ERR_HIP;
+    // the events carry no memory fence; a device-wide wait orders the reads
+    if (g_prof.used > 0 && hipDeviceSynchronize() != hipSuccess) st = DCR_ERR_HIP;
     for (int i = 0; i < g_prof.used && st == DCR_OK; ++i) {
         float t = 0.f;
         if (hipEventElapsedTime(&t, g_prof.ev[2 * i], g_prof.ev[2 * i + 1]) != hipSuccess) {

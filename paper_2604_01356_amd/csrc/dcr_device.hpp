@@ -177,6 +177,22 @@ __device__ __forceinline__ RawChunk<Tin> load_raw(const Tin* __restrict__ p) {
     return r;
 }
 
+// The same from an address aligned only to the element size (a segment of a
+// concatenated batch may start anywhere): vector loads of element-aligned
+// addresses, which global memory accepts on this chip.
+template <typename Tin>
+__device__ __forceinline__ RawChunk<Tin> load_raw_any(const Tin* __restrict__ p) {
+    RawChunk<Tin> r;
+    if constexpr (sizeof(Tin) == 4) {
+#pragma unroll
+        for (int v = 0; v < kLane / 4; ++v) __builtin_memcpy(&r.v[v], p + 4 * v, sizeof(f32x4));
+    } else {
+#pragma unroll
+        for (int v = 0; v < kLane / 2; ++v) __builtin_memcpy(&r.v[v], p + 2 * v, sizeof(f64x2));
+    }
+    return r;
+}
+
 // Left-to-right binary64 sum of a raw chunk; also folds its elements into a
 // running minimum (in the input precision) used to detect negative weights.
 template <typename Tin>

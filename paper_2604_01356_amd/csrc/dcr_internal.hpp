@@ -7,6 +7,16 @@
 
 namespace dcr {
 
+// Optional timing of the next kernel launch: when `start` and `stop` are set,
+// the launch records its own start and end into them (hipExtLaunchKernel), so
+// the interval is the kernel alone.  `launches` counts every launch made.
+struct LaunchEvents {
+    hipEvent_t start = nullptr;
+    hipEvent_t stop = nullptr;
+    int64_t launches = 0;
+};
+extern LaunchEvents g_launch_events;
+
 constexpr int kPrecFP64 = 0;
 constexpr int kPrecFP32 = 1;
 
@@ -50,11 +60,16 @@ bool finish_fits(const WArgs& wa, const ZArgs& za);
 constexpr int64_t kDenseRatio = 4;
 bool map_is_dense(int64_t M, int64_t N);
 int64_t dense_chunks(int64_t N);
-// Runs k_map_dense and then k_map_wide for the chunks it flags in `wide`
-// (dense_chunks(N) int32 flags, written before they are read).
+// k_map_dense: merges each chunk of 4096 draws and flags in `wide`
+// (dense_chunks(N) int32 flags) the chunks whose span is too wide to merge;
+// launch_map_wide then places the draws of the flagged chunks.
 hipError_t launch_map_dense(int prec, const void* w, const WArgs& wa, const ZArgs& za,
                             const SharedArgs& sh, double* u_out, int32_t* r, int32_t* wide,
                             int vec_ok, hipStream_t s);
+// the flagged (wide-span) chunks left by launch_map_dense
+hipError_t launch_map_wide(int prec, const void* w, const WArgs& wa, const ZArgs& za,
+                           const SharedArgs& sh, int32_t* r, const int32_t* wide, int vec_ok,
+                           hipStream_t s);
 
 hipError_t launch_carries(const WArgs& wa, const ZArgs& za, const SharedArgs& sh,
                           int32_t* dev_status, double* total_out, hipStream_t s);
@@ -69,5 +84,41 @@ hipError_t launch_map_fused(int prec, const void* w, const WArgs& wa, const ZArg
                             hipStream_t s);
 hipError_t launch_map_w(const double* W, int64_t M, const double* u, int64_t N, int32_t* r,
                         hipStream_t s);
+
+// Batched form: B independent filters over concatenated arrays.  Filter b
+// owns weights [w_off[b], w_off[b+1]) and draws [n_off[b], n_off[b+1]); its
+// blocks, scans and draws follow the single-distribution structure relative
+// to its own start, with Philox stream id b, so each filter's result equals a
+// single call on its weights.
+struct BatchArgs {
+    const int64_t* w_off;   // [B+1] caller's weight offsets (w_off[0] == 0)
+    const int64_t* n_off;   // [B+1] caller's draw offsets (n_off[0] == 0)
+    int32_t B;
+    uint64_t seed;
+    int64_t wt_cap, zt_cap, mc_cap;   // launch sizes: weight blocks, spacing blocks, map chunks
+    int64_t sumM_cap, sumN_cap;
+    int64_t* wt_base;       // [B+1] first weight block of each filter (k_batch_plan)
+    int64_t* zt_base;       // [B+1] first spacing block
+    int64_t* mc_base;       // [B+1] first map chunk (64 draws)
+    int32_t* head;          // [0] plan status, [1] batch status
+    double* wt_tot;         // [wt_cap] weight-block totals
+    double* wt_beta;        // [wt_cap] weight-block ends (per filter)
+    double* wt_sub;         // [wt_cap * 128] sub-tile ends
+    double* zt_tot;         // [zt_cap]
+    double* zt_beta;        // [zt_cap]
+    double* zrel;           // [sumN + B] in-block spacing prefixes, filter b at n_off[b] + b
+    int32_t* seg_status;    // [B]
+    double* seg_totals;     // [2B] weight total, spacing total
+};
+constexpr int kPlanThreads = 1024;
+constexpr int64_t kBatchWBlock = 32768;
+constexpr int64_t kBatchZBlock = 4096;
+constexpr int64_t kBatchChunk = 64;
+// The batched launches, in order: plan, reduce, carries, map.
+hipError_t launch_batch_plan(const BatchArgs& ba, int32_t* dev_status, hipStream_t s);
+hipError_t launch_reduce_batched(int prec, const void* w, const BatchArgs& ba, hipStream_t s);
+hipError_t launch_carries_batched(const BatchArgs& ba, hipStream_t s);
+hipError_t launch_map_batched(int prec, const void* w, const BatchArgs& ba, int32_t* r,
+                              int32_t* dev_status, hipStream_t s);
 
 }  // namespace dcr

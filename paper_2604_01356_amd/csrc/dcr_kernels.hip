@@ -14,6 +14,9 @@
 //   k_map_w             inverse CMF against a given W (stage 3 alone)
 // The summation structure that fixes the bits of W and u is described in
 // dcr_device.hpp.
+#include <hip/hip_ext.h>
+#include <hip/hip_runtime.h>
+
 #include "dcr_device.hpp"
 #include "dcr_internal.hpp"
 
@@ -60,23 +63,15 @@ __device__ __forceinline__ void wait_vm(int outstanding) {
     __builtin_amdgcn_sched_barrier(0);
 }
 
-template <typename Tin, int P>
-__global__ __launch_bounds__(kThreads) void k_reduce(const Tin* __restrict__ w, WArgs wa, ZArgs za,
-                                                     int vec_ok) {
-    __shared__ __attribute__((aligned(16))) unsigned char sb0[ReduceSmem<Tin>::kBuf0];
-    __shared__ __attribute__((aligned(16))) unsigned char sb1[ReduceSmem<Tin>::kBuf];
-    __shared__ __attribute__((aligned(16))) unsigned char sb2[ReduceSmem<Tin>::kBuf];
-    double* lane_tot = reinterpret_cast<double*>(sb0);   // [kWIters][kThreads]
-    double* sub_tot = lane_tot + kWIters * kThreads;      // [kWSubPerBlock]
-    double* sub_end = sub_tot + kWSubPerBlock;            // [kWSubPerBlock]
+// Spacing block g of za: z_i = -log v_i (Alg. 1) for its draws, their
+// in-block prefix sums (stored) and the block total.  All threads call it.
+template <int P>
+__device__ __forceinline__ void reduce_z_block(const ZArgs& za, int64_t g, double* lane_tot,
+                                               double* sub_tot) {
     const int t = threadIdx.x;
     const int row = t / kRowLanes;
     const int lane = t % kRowLanes;
-
-    if (static_cast<int64_t>(blockIdx.x) < za.nb) {
-        // ---- exponential spacings z_i = -log v_i, i = 0..N (Alg. 1), and
-        //      their in-block prefix sums (stored) and block total ----
-        const int64_t g = blockIdx.x;
+    {
         const int64_t i0 = g * kZBlock + static_cast<int64_t>(t) * kLane;
         const int nv = clamp_count(za.N + 1 - i0, kLane);
         double p[kLane];
@@ -120,17 +115,32 @@ __global__ __launch_bounds__(kThreads) void k_reduce(const Tin* __restrict__ w, 
             for (int k = 0; k < nv; ++k) za.zrel[i0 + k] = zr[k];
         }
         if (t == 0) za.blk_tot[g] = total;
-        return;
     }
+}
 
-    // ---- weights: lane-chunk totals, sub-tile totals, sub-tile ends ----
-    const int64_t b = static_cast<int64_t>(blockIdx.x) - za.nb;
+// Weight block b of wa: lane-chunk totals, sub-tile totals, the stored
+// sub-tile ends and the block total (NaN for an inadmissible block).  The
+// three LDS buffers stream binary32 weights; sb0 is also the epilogue's
+// scratch.  All threads call it.
+template <typename Tin>
+__device__ __forceinline__ void reduce_w_block(const Tin* __restrict__ w, const WArgs& wa, int64_t b,
+                                               int vec_ok, unsigned char* sb0, unsigned char* sb1,
+                                               unsigned char* sb2) {
+    double* lane_tot = reinterpret_cast<double*>(sb0);   // [kWIters][kThreads]
+    double* sub_tot = lane_tot + kWIters * kThreads;      // [kWSubPerBlock]
+    double* sub_end = sub_tot + kWSubPerBlock;            // [kWSubPerBlock]
+    const int t = threadIdx.x;
+    const int row = t / kRowLanes;
+    const int lane = t % kRowLanes;
     const int64_t blk0 = b * kWBlock;
     int bad = 0;
     double lt[kWIters];
-    const bool full = (vec_ok & 1) && blk0 + kWBlock <= wa.M;
+    const bool full = blk0 + kWBlock <= wa.M;
+    const bool aligned = (vec_ok & 1) != 0;
+    bool done = false;
     if constexpr (sizeof(Tin) == 4) {
-        if (full) {
+        if (full && aligned) {
+            done = true;
             float* const bufs[kStreamBufs] = {reinterpret_cast<float*>(sb0),
                                               reinterpret_cast<float*>(sb1),
                                               reinterpret_cast<float*>(sb2)};
@@ -170,23 +180,23 @@ __global__ __launch_bounds__(kThreads) void k_reduce(const Tin* __restrict__ w, 
             // NaN and +inf reach the block total (checked below); negatives the minimum
             bad = (mn < 0.0f) ? 1 : 0;
         }
-    } else {
-        if (full) {
-            // binary64: lane-strided loads, the next round issued before summing
-            const Tin* base = w + blk0 + row * kSub + lane * kLane;
-            Tin mn = static_cast<Tin>(0);
-            RawChunk<Tin> cur = load_raw<Tin>(base);
-            mn = cur.raw(0);
+    }
+    if (full && !done) {
+        // binary64, or binary32 that is not 16-byte aligned: lane-strided
+        // vector loads (element-aligned), the next round issued before summing
+        const Tin* base = w + blk0 + row * kSub + lane * kLane;
+        Tin mn = static_cast<Tin>(0);
+        RawChunk<Tin> cur = load_raw_any<Tin>(base);
+        mn = cur.raw(0);
 #pragma unroll
-            for (int it = 0; it < kWIters; ++it) {
-                RawChunk<Tin> nxt;
-                if (it + 1 < kWIters) nxt = load_raw<Tin>(base + (it + 1) * kRows * kSub);
-                lt[it] = raw_sum<Tin>(cur, mn);
-                if (it + 1 < kWIters) cur = nxt;
-                __builtin_amdgcn_sched_barrier(0);
-            }
-            bad = (mn < static_cast<Tin>(0)) ? 1 : 0;
+        for (int it = 0; it < kWIters; ++it) {
+            RawChunk<Tin> nxt;
+            if (it + 1 < kWIters) nxt = load_raw_any<Tin>(base + (it + 1) * kRows * kSub);
+            lt[it] = raw_sum<Tin>(cur, mn);
+            if (it + 1 < kWIters) cur = nxt;
+            __builtin_amdgcn_sched_barrier(0);
         }
+        bad = (mn < static_cast<Tin>(0)) ? 1 : 0;
     }
     if (!full) {
 #pragma unroll 1
@@ -236,6 +246,20 @@ __global__ __launch_bounds__(kThreads) void k_reduce(const Tin* __restrict__ w, 
         const double tot = sub_end[kWSubPerBlock - 1];
         wa.blk_tot[b] = (bad || !(tot < __builtin_huge_val())) ? __builtin_nan("") : tot;
     }
+}
+
+template <typename Tin, int P>
+__global__ __launch_bounds__(kThreads) void k_reduce(const Tin* __restrict__ w, WArgs wa, ZArgs za,
+                                                     int vec_ok) {
+    __shared__ __attribute__((aligned(16))) unsigned char sb0[ReduceSmem<Tin>::kBuf0];
+    __shared__ __attribute__((aligned(16))) unsigned char sb1[ReduceSmem<Tin>::kBuf];
+    __shared__ __attribute__((aligned(16))) unsigned char sb2[ReduceSmem<Tin>::kBuf];
+    if (static_cast<int64_t>(blockIdx.x) < za.nb) {
+        double* lane_tot = reinterpret_cast<double*>(sb0);
+        reduce_z_block<P>(za, blockIdx.x, lane_tot, lane_tot + kThreads);
+        return;
+    }
+    reduce_w_block<Tin>(w, wa, static_cast<int64_t>(blockIdx.x) - za.nb, vec_ok, sb0, sb1, sb2);
 }
 
 // ---------------------------------------------------------------------------
@@ -428,9 +452,8 @@ __device__ __forceinline__ void store_uniforms(double* __restrict__ u, int64_t i
 // ---------------------------------------------------------------------------
 // k_carries: block-total scans (weights and spacings), totals and validity.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kScanThreads) void k_carries(WArgs wa, ZArgs za, SharedArgs sh,
-                                                          int32_t* dev_status, double* total_out) {
-    __shared__ ScanLds L;
+__device__ __forceinline__ void carries_body(const WArgs& wa, const ZArgs& za, const SharedArgs& sh,
+                                             int32_t* dev_status, double* total_out, ScanLds& L) {
     const int t = threadIdx.x;
     ScanIn si[2];
     scan_load(wa.blk_tot, wa.nb, si[0]);
@@ -451,6 +474,12 @@ __global__ __launch_bounds__(kScanThreads) void k_carries(WArgs wa, ZArgs za, Sh
         sh.status[0] = status;
         if (dev_status) *dev_status = status;
     }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_carries(WArgs wa, ZArgs za, SharedArgs sh,
+                                                          int32_t* dev_status, double* total_out) {
+    __shared__ ScanLds L;
+    carries_body(wa, za, sh, dev_status, total_out, L);
 }
 
 // ---------------------------------------------------------------------------
@@ -719,13 +748,14 @@ __device__ void map_quad(const Tin* __restrict__ w, const WArgs& wa, const doubl
     r[i] = static_cast<int32_t>(jr);
 }
 
-// Map with the scanned block ends read from memory (after k_carries).
+// Map of draws 64c .. 64c+63 with the scanned block ends read from memory
+// (after k_carries).  All threads call it; sbeta is kBetaLds doubles of LDS.
 template <typename Tin>
-__global__ __launch_bounds__(kThreads) void k_map_fused(const Tin* __restrict__ w, WArgs wa, ZArgs za,
-                                                        SharedArgs sh, double* __restrict__ u_out,
-                                                        int32_t* __restrict__ r, int vec_ok) {
+__device__ __forceinline__ void map_chunk(const Tin* __restrict__ w, const WArgs& wa, const ZArgs& za,
+                                          const SharedArgs& sh, double* __restrict__ u_out,
+                                          int32_t* __restrict__ r, int vec_ok, int64_t c,
+                                          double* sbeta) {
     const int64_t N = za.N;
-    __shared__ double sbeta[kBetaLds];
     const int t = threadIdx.x;
     const int64_t nb = wa.nb;
     const int64_t kstride = (nb + kBetaLds - 1) / kBetaLds;
@@ -734,7 +764,7 @@ __global__ __launch_bounds__(kThreads) void k_map_fused(const Tin* __restrict__ 
         const int64_t b = (static_cast<int64_t>(q) + 1) * kstride - 1;
         sbeta[q] = wa.beta[b < nb ? b : nb - 1];
     }
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * kUPerWG + (t / kQuad);
+    const int64_t i = c * kUPerWG + (t / kQuad);
     const bool ok = sh.status[0] == kStatusOk;
     double x = 0.0;
     if (i < N) {
@@ -749,6 +779,14 @@ __global__ __launch_bounds__(kThreads) void k_map_fused(const Tin* __restrict__ 
         return;
     }
     map_quad<Tin>(w, wa, sbeta, kstride, ns, x, i, t & (kQuad - 1), r, vec_ok);
+}
+
+template <typename Tin>
+__global__ __launch_bounds__(kThreads) void k_map_fused(const Tin* __restrict__ w, WArgs wa, ZArgs za,
+                                                        SharedArgs sh, double* __restrict__ u_out,
+                                                        int32_t* __restrict__ r, int vec_ok) {
+    __shared__ double sbeta[kBetaLds];
+    map_chunk<Tin>(w, wa, za, sh, u_out, r, vec_ok, blockIdx.x, sbeta);
 }
 
 // ---------------------------------------------------------------------------
@@ -781,6 +819,7 @@ __global__ __launch_bounds__(kThreads) void k_map_dense(const Tin* __restrict__ 
     __shared__ double uends[2];
     __shared__ double ltot[kThreads];
     __shared__ double wlast[kThreads];   // last normalised weight of each thread's 16
+    __shared__ int32_t rloc[kDenseU];    // the chunk's indices, stored coalesced at the end
     __shared__ int64_t span_ends[2];
     const int t = threadIdx.x;
     const int64_t N = za.N;
@@ -911,10 +950,21 @@ __global__ __launch_bounds__(kThreads) void k_map_dense(const Tin* __restrict__ 
             int cnt = 0;
 #pragma unroll
             for (int k = 0; k < kLane; ++k) cnt += (wv[k] < x) ? 1 : 0;
-            r[c0 + iu] = static_cast<int32_t>(jbase + cnt);
+            rloc[iu] = static_cast<int32_t>(jbase + cnt);
         }
         wprev_window = wlast[nw * kRowLanes - 1];
         lds_barrier();   // ltot / wlast are rewritten by the next window
+    }
+    // every draw of the chunk has been placed in exactly one thread's bins
+    const int i0 = t * kDensePer;
+    if (nmine == kDensePer && (reinterpret_cast<uintptr_t>(r + iu0) & 15) == 0) {
+        int4* dst = reinterpret_cast<int4*>(r + iu0);
+#pragma unroll
+        for (int v = 0; v < kDensePer / 4; ++v)
+            dst[v] = make_int4(rloc[i0 + 4 * v], rloc[i0 + 4 * v + 1], rloc[i0 + 4 * v + 2],
+                               rloc[i0 + 4 * v + 3]);
+    } else {
+        for (int q = 0; q < nmine; ++q) r[iu0 + q] = rloc[i0 + q];
     }
 }
 
@@ -1029,14 +1079,207 @@ __global__ __launch_bounds__(kThreads) void k_map_w(const double* __restrict__ W
 }
 
 // ---------------------------------------------------------------------------
+// Batched form.  k_batch_plan counts each filter's weight blocks, spacing
+// blocks and map chunks and scans the counts into per-filter bases; the other
+// kernels are launched over capacity-sized grids and map their workgroup to a
+// filter by a search of those bases.  Each then runs the single-distribution
+// block code on the filter's own view of the arrays.
+// ---------------------------------------------------------------------------
+static_assert(kBatchChunk == kUPerWG, "a map chunk is one workgroup of quads");
+static_assert(kBatchWBlock == kWBlock && kBatchZBlock == kZBlock, "block sizes");
+constexpr int kStatusInvalid = 1;
+constexpr int kStatusCapacity = 4;
+constexpr int64_t kMaxSegM = 2147483647LL;
+constexpr int64_t kMaxSegN = 2147483646LL;
+
+__global__ __launch_bounds__(kPlanThreads) void k_batch_plan(BatchArgs ba, int32_t* dev_status) {
+    __shared__ int64_t sc[3][kPlanThreads];
+    __shared__ int64_t carry[3];
+    __shared__ int err;
+    const int t = threadIdx.x;
+    if (t == 0) {
+        carry[0] = carry[1] = carry[2] = 0;
+        err = (ba.w_off[0] != 0 || ba.n_off[0] != 0) ? kStatusInvalid : kStatusOk;
+    }
+    __syncthreads();
+    for (int64_t base = 0; base < ba.B; base += kPlanThreads) {
+        const int64_t b = base + t;
+        int64_t cnt[3] = {0, 0, 0};
+        if (b < ba.B) {
+            const int64_t M = ba.w_off[b + 1] - ba.w_off[b];
+            const int64_t N = ba.n_off[b + 1] - ba.n_off[b];
+            if (M < 1 || M > kMaxSegM || N < 0 || N > kMaxSegN) {
+                err = kStatusInvalid;
+            } else {
+                cnt[0] = (M + kBatchWBlock - 1) / kBatchWBlock;
+                cnt[1] = (N > 0) ? (N + 1 + kBatchZBlock - 1) / kBatchZBlock : 0;
+                cnt[2] = (N + kBatchChunk - 1) / kBatchChunk;
+            }
+        }
+        // inclusive scans of the three counts (Hillis-Steele over the workgroup)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) sc[k][t] = cnt[k];
+        __syncthreads();
+        for (int off = 1; off < kPlanThreads; off <<= 1) {
+            int64_t add[3] = {0, 0, 0};
+            if (t >= off) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) add[k] = sc[k][t - off];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < 3; ++k) sc[k][t] += add[k];
+            __syncthreads();
+        }
+        if (b < ba.B) {
+            ba.wt_base[b] = carry[0] + sc[0][t] - cnt[0];
+            ba.zt_base[b] = carry[1] + sc[1][t] - cnt[1];
+            ba.mc_base[b] = carry[2] + sc[2][t] - cnt[2];
+        }
+        __syncthreads();
+        if (t == kPlanThreads - 1) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) carry[k] += sc[k][t];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        ba.wt_base[ba.B] = carry[0];
+        ba.zt_base[ba.B] = carry[1];
+        ba.mc_base[ba.B] = carry[2];
+        int st = err;
+        if (st == kStatusOk &&
+            (carry[0] > ba.wt_cap || carry[1] > ba.zt_cap || carry[2] > ba.mc_cap ||
+             ba.w_off[ba.B] > ba.sumM_cap || ba.n_off[ba.B] > ba.sumN_cap))
+            st = kStatusCapacity;
+        ba.head[0] = st;
+        ba.head[1] = st;
+        if (dev_status) *dev_status = st;
+    }
+}
+
+// Largest b in [0, B) with base[b] <= x, for non-decreasing base with
+// base[0] = 0 <= x: a 64-ary search, one element per lane per step.  Every
+// lane of the wave must call it.
+__device__ __forceinline__ int find_segment(const int64_t* __restrict__ base, int B, int64_t x) {
+    const int lane = threadIdx.x & 63;
+    int lo = 0, hi = B;
+    while (hi - lo > 1) {
+        const int stride = (hi - lo + 63) / 64;
+        const int idx = lo + lane * stride;
+        const bool le = idx < hi && base[idx] <= x;
+        const int k = __popcll(__ballot(le));   // a prefix of the lanes, k >= 1
+        lo = lo + (k - 1) * stride;
+        hi = (lo + stride < hi) ? lo + stride : hi;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ WArgs seg_wargs(const BatchArgs& ba, int b) {
+    WArgs a;
+    const int64_t t0 = ba.wt_base[b];
+    a.M = ba.w_off[b + 1] - ba.w_off[b];
+    a.nb = ba.wt_base[b + 1] - t0;
+    a.blk_tot = ba.wt_tot + t0;
+    a.beta = ba.wt_beta + t0;
+    a.sub_end = ba.wt_sub + t0 * kWSubPerBlock;
+    return a;
+}
+
+__device__ __forceinline__ ZArgs seg_zargs(const BatchArgs& ba, int b) {
+    ZArgs a;
+    const int64_t t0 = ba.zt_base[b];
+    a.N = ba.n_off[b + 1] - ba.n_off[b];
+    a.nb = ba.zt_base[b + 1] - t0;
+    a.seed = ba.seed;
+    a.stream = static_cast<uint64_t>(b);
+    a.zrel = ba.zrel + ba.n_off[b] + b;
+    a.blk_tot = ba.zt_tot + t0;
+    a.beta = ba.zt_beta + t0;
+    return a;
+}
+
+__device__ __forceinline__ SharedArgs seg_shared(const BatchArgs& ba, int b) {
+    SharedArgs a;
+    a.status = ba.seg_status + b;
+    a.totals = ba.seg_totals + 2 * static_cast<int64_t>(b);
+    return a;
+}
+
+__device__ __forceinline__ int aligned16_flag(const void* p) {
+    return (reinterpret_cast<uintptr_t>(p) & 15) == 0 ? 1 : 0;
+}
+
+// Workgroups [0, zt_cap) draw spacing blocks, the rest reduce weight blocks.
+template <typename Tin, int P>
+__global__ __launch_bounds__(kThreads) void k_reduce_batched(const Tin* __restrict__ w, BatchArgs ba) {
+    __shared__ __attribute__((aligned(16))) unsigned char sb0[ReduceSmem<Tin>::kBuf0];
+    __shared__ __attribute__((aligned(16))) unsigned char sb1[ReduceSmem<Tin>::kBuf];
+    __shared__ __attribute__((aligned(16))) unsigned char sb2[ReduceSmem<Tin>::kBuf];
+    if (ba.head[0] != kStatusOk) return;
+    int64_t tile = blockIdx.x;
+    if (tile < ba.zt_cap) {
+        if (tile >= ba.zt_base[ba.B]) return;
+        const int b = find_segment(ba.zt_base, ba.B, tile);
+        const ZArgs za = seg_zargs(ba, b);
+        double* lane_tot = reinterpret_cast<double*>(sb0);
+        reduce_z_block<P>(za, tile - ba.zt_base[b], lane_tot, lane_tot + kThreads);
+        return;
+    }
+    tile -= ba.zt_cap;
+    if (tile >= ba.wt_base[ba.B]) return;
+    const int b = find_segment(ba.wt_base, ba.B, tile);
+    const WArgs wa = seg_wargs(ba, b);
+    const Tin* ws = w + ba.w_off[b];
+    reduce_w_block<Tin>(ws, wa, tile - ba.wt_base[b], aligned16_flag(ws), sb0, sb1, sb2);
+}
+
+// One workgroup per filter: its block-total scans, totals and status.
+__global__ __launch_bounds__(kScanThreads) void k_carries_batched(BatchArgs ba) {
+    __shared__ ScanLds L;
+    if (ba.head[0] != kStatusOk) return;
+    const int b = blockIdx.x;
+    const SharedArgs sh = seg_shared(ba, b);
+    carries_body(seg_wargs(ba, b), seg_zargs(ba, b), sh, nullptr, nullptr, L);
+    if (threadIdx.x == 0 && sh.status[0] != kStatusOk) atomicMax(ba.head + 1, kStatusBadWeights);
+}
+
+// 64 draws of one filter per workgroup; indices are local to the filter.
+template <typename Tin>
+__global__ __launch_bounds__(kThreads) void k_map_batched(const Tin* __restrict__ w, BatchArgs ba,
+                                                          int32_t* __restrict__ r,
+                                                          int32_t* dev_status) {
+    __shared__ double sbeta[kBetaLds];
+    const int plan = ba.head[0];
+    if (blockIdx.x == 0 && threadIdx.x == 0 && dev_status)
+        *dev_status = (plan != kStatusOk) ? plan : ba.head[1];
+    if (plan != kStatusOk) return;
+    const int64_t c = blockIdx.x;
+    if (c >= ba.mc_base[ba.B]) return;
+    const int b = find_segment(ba.mc_base, ba.B, c);
+    const Tin* ws = w + ba.w_off[b];
+    map_chunk<Tin>(ws, seg_wargs(ba, b), seg_zargs(ba, b), seg_shared(ba, b), nullptr,
+                   r + ba.n_off[b], aligned16_flag(ws), c - ba.mc_base[b], sbeta);
+}
+
+// ---------------------------------------------------------------------------
 // Host-side launchers
 // ---------------------------------------------------------------------------
+// Every kernel launch of the library goes through here: the launch records
+// its own start and end into the timing events when they are set.
+template <typename K, typename... A>
+static void launch(K kernel, dim3 grid, dim3 block, uint32_t shmem, hipStream_t s, A... args) {
+    hipExtLaunchKernelGGL(kernel, grid, block, shmem, s, g_launch_events.start,
+                          g_launch_events.stop, 0, args...);
+    ++g_launch_events.launches;
+}
+
 template <typename Tin, int P>
 static hipError_t launch_reduce_t(const void* w, const WArgs& wa, const ZArgs& za, int vec_ok,
                                   hipStream_t s) {
     const int64_t grid = wa.nb + za.nb;
     if (grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_reduce<Tin, P>), dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s,
+    launch((k_reduce<Tin, P>), dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s,
                        static_cast<const Tin*>(w), wa, za, vec_ok);
     return hipGetLastError();
 }
@@ -1049,7 +1292,7 @@ hipError_t launch_reduce(int prec, const void* w, const WArgs& wa, const ZArgs& 
 
 hipError_t launch_carries(const WArgs& wa, const ZArgs& za, const SharedArgs& sh,
                           int32_t* dev_status, double* total_out, hipStream_t s) {
-    hipLaunchKernelGGL(k_carries, dim3(1), dim3(kScanThreads), 0, s, wa, za, sh, dev_status,
+    launch(k_carries, dim3(1), dim3(kScanThreads), 0, s, wa, za, sh, dev_status,
                        total_out);
     return hipGetLastError();
 }
@@ -1059,10 +1302,10 @@ hipError_t launch_materialize_w(int prec, const void* w, const WArgs& wa, const 
     const int64_t grid = wa.nb * kWIters;
     if (grid <= 0) return hipSuccess;
     if (prec == kPrecFP32)
-        hipLaunchKernelGGL(k_materialize_w<float>, dim3(static_cast<unsigned>(grid)), dim3(kThreads),
+        launch(k_materialize_w<float>, dim3(static_cast<unsigned>(grid)), dim3(kThreads),
                            0, s, static_cast<const float*>(w), wa, sh, W, vec_ok);
     else
-        hipLaunchKernelGGL(k_materialize_w<double>, dim3(static_cast<unsigned>(grid)),
+        launch(k_materialize_w<double>, dim3(static_cast<unsigned>(grid)),
                            dim3(kThreads), 0, s, static_cast<const double*>(w), wa, sh, W, vec_ok);
     return hipGetLastError();
 }
@@ -1070,7 +1313,7 @@ hipError_t launch_materialize_w(int prec, const void* w, const WArgs& wa, const 
 hipError_t launch_materialize_u(const ZArgs& za, const SharedArgs& sh, double* u, hipStream_t s) {
     if (za.nb <= 0 || za.N <= 0) return hipSuccess;
     const int vec_out = (reinterpret_cast<uintptr_t>(u) % 16) == 0 ? 1 : 0;
-    hipLaunchKernelGGL(k_materialize_u, dim3(static_cast<unsigned>(za.nb)), dim3(kThreads), 0, s, za,
+    launch(k_materialize_u, dim3(static_cast<unsigned>(za.nb)), dim3(kThreads), 0, s, za,
                        sh, u, vec_out);
     return hipGetLastError();
 }
@@ -1081,10 +1324,10 @@ hipError_t launch_map_fused(int prec, const void* w, const WArgs& wa, const ZArg
     if (za.N <= 0) return hipSuccess;
     const int64_t grid = (za.N + kUPerWG - 1) / kUPerWG;
     if (prec == kPrecFP32)
-        hipLaunchKernelGGL(k_map_fused<float>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0,
+        launch(k_map_fused<float>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0,
                            s, static_cast<const float*>(w), wa, za, sh, u_out, r, vec_ok);
     else
-        hipLaunchKernelGGL(k_map_fused<double>, dim3(static_cast<unsigned>(grid)), dim3(kThreads),
+        launch(k_map_fused<double>, dim3(static_cast<unsigned>(grid)), dim3(kThreads),
                            0, s, static_cast<const double*>(w), wa, za, sh, u_out, r, vec_ok);
     return hipGetLastError();
 }
@@ -1097,17 +1340,24 @@ hipError_t launch_map_dense(int prec, const void* w, const WArgs& wa, const ZArg
     if (za.N <= 0) return hipSuccess;
     const int64_t grid = dense_chunks(za.N);
     if (prec == kPrecFP32)
-        hipLaunchKernelGGL(k_map_dense<float>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0,
+        launch(k_map_dense<float>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0,
                            s, static_cast<const float*>(w), wa, za, sh, u_out, r, wide, vec_ok);
     else
-        hipLaunchKernelGGL(k_map_dense<double>, dim3(static_cast<unsigned>(grid)), dim3(kThreads),
+        launch(k_map_dense<double>, dim3(static_cast<unsigned>(grid)), dim3(kThreads),
                            0, s, static_cast<const double*>(w), wa, za, sh, u_out, r, wide, vec_ok);
-    if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+    return hipGetLastError();
+}
+
+hipError_t launch_map_wide(int prec, const void* w, const WArgs& wa, const ZArgs& za,
+                           const SharedArgs& sh, int32_t* r, const int32_t* wide, int vec_ok,
+                           hipStream_t s) {
+    if (za.N <= 0) return hipSuccess;
+    const int64_t grid = dense_chunks(za.N);
     if (prec == kPrecFP32)
-        hipLaunchKernelGGL(k_map_wide<float>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0,
+        launch(k_map_wide<float>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0,
                            s, static_cast<const float*>(w), wa, za, sh, r, wide, vec_ok);
     else
-        hipLaunchKernelGGL(k_map_wide<double>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0,
+        launch(k_map_wide<double>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0,
                            s, static_cast<const double*>(w), wa, za, sh, r, wide, vec_ok);
     return hipGetLastError();
 }
@@ -1124,10 +1374,10 @@ hipError_t launch_finish(int prec, const void* w, const WArgs& wa, const ZArgs& 
                          int vec_ok, hipStream_t s) {
     const int64_t grid = (za.N + kUPerWG - 1) / kUPerWG;
     if (prec == kPrecFP32)
-        hipLaunchKernelGGL(k_finish<float>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s,
+        launch(k_finish<float>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s,
                            static_cast<const float*>(w), wa, za, sh, dev_status, u_out, r, vec_ok);
     else
-        hipLaunchKernelGGL(k_finish<double>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0,
+        launch(k_finish<double>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0,
                            s, static_cast<const double*>(w), wa, za, sh, dev_status, u_out, r,
                            vec_ok);
     return hipGetLastError();
@@ -1137,8 +1387,42 @@ hipError_t launch_map_w(const double* W, int64_t M, const double* u, int64_t N, 
                         hipStream_t s) {
     if (N <= 0) return hipSuccess;
     const int64_t grid = (N + kThreads - 1) / kThreads;
-    hipLaunchKernelGGL(k_map_w, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s, W, M, u, N,
+    launch(k_map_w, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s, W, M, u, N,
                        r);
+    return hipGetLastError();
+}
+
+
+hipError_t launch_batch_plan(const BatchArgs& ba, int32_t* dev_status, hipStream_t s) {
+    launch(k_batch_plan, dim3(1), dim3(kPlanThreads), 0, s, ba, dev_status);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_batched(int prec, const void* w, const BatchArgs& ba, hipStream_t s) {
+    const unsigned grid = static_cast<unsigned>(ba.zt_cap + ba.wt_cap);
+    if (prec == kPrecFP32)
+        launch(k_reduce_batched<float, kPrecFP32>, dim3(grid), dim3(kThreads), 0, s,
+               static_cast<const float*>(w), ba);
+    else
+        launch(k_reduce_batched<double, kPrecFP64>, dim3(grid), dim3(kThreads), 0, s,
+               static_cast<const double*>(w), ba);
+    return hipGetLastError();
+}
+
+hipError_t launch_carries_batched(const BatchArgs& ba, hipStream_t s) {
+    launch(k_carries_batched, dim3(static_cast<unsigned>(ba.B)), dim3(kScanThreads), 0, s, ba);
+    return hipGetLastError();
+}
+
+hipError_t launch_map_batched(int prec, const void* w, const BatchArgs& ba, int32_t* r,
+                              int32_t* dev_status, hipStream_t s) {
+    const unsigned grid = static_cast<unsigned>(ba.mc_cap);
+    if (prec == kPrecFP32)
+        launch(k_map_batched<float>, dim3(grid), dim3(kThreads), 0, s, static_cast<const float*>(w),
+               ba, r, dev_status);
+    else
+        launch(k_map_batched<double>, dim3(grid), dim3(kThreads), 0, s,
+               static_cast<const double*>(w), ba, r, dev_status);
     return hipGetLastError();
 }
 

@@ -31,7 +31,8 @@ def declared_functions():
 def test_header_declares_entry_points():
     names = declared_functions()
     for n in ["dcr_workspace_bytes", "dcr_cumulative_weights", "dcr_sorted_uniforms",
-              "dcr_inverse_cmf", "dcr_resample", "dcr_status_string"]:
+              "dcr_inverse_cmf", "dcr_resample", "dcr_status_string",
+              "dcr_batched_workspace_bytes", "dcr_resample_batched"]:
         assert n in names
 
 
@@ -98,6 +99,48 @@ def test_host_validation_stages(lib):
     assert lib.dcr_inverse_cmf(FAKE, 0, FAKE, 10, FAKE, None, 0, None) == 1
     assert lib.dcr_inverse_cmf(None, 10, FAKE, 10, FAKE, None, 0, None) == 1
     assert lib.dcr_inverse_cmf(FAKE, 10, FAKE, 0, None, None, 0, None) == 0  # N = 0: no-op
+
+
+def test_batched_workspace_bytes(lib):
+    import paper_2604_01356_amd as dcr
+    a = dcr.dcr_batched_workspace_bytes(1, 1, 0)
+    b = dcr.dcr_batched_workspace_bytes(4096, 600_000_000, 15_000_000, dcr.DCR_FP32_COMP)
+    assert 0 < a < b and b % 256 == 0
+    for bad in [(0, 10, 10), (-3, 10, 10), (10, 9, 10), (10, 100, -1), (1 << 25, 1 << 26, 0),
+                (4, 1 << 41, 0), (4, 100, 1 << 41)]:
+        with pytest.raises(dcr.DcrError) as e:
+            dcr.dcr_batched_workspace_bytes(*bad)
+        assert e.value.code == 1
+    with pytest.raises(dcr.DcrError) as e:
+        dcr.dcr_batched_workspace_bytes(4, 100, 10, 3)
+    assert e.value.code == 2
+
+
+def test_host_validation_batched(lib):
+    n = ctypes.c_size_t(0)
+    assert lib.dcr_batched_workspace_bytes(8, 1000, 100, 1, ctypes.byref(n)) == 0
+    ws = n.value
+    f = lib.dcr_resample_batched
+    ok = (FAKE, FAKE, FAKE, 8, 1000, 100, 1, 1, FAKE, None, None, FAKE, ws, None)
+
+    def call(**kw):
+        names = ["w", "w_off", "n_off", "B", "sumM", "sumN", "seed", "p", "r", "seg", "st",
+                 "ws", "ws_bytes", "stream"]
+        args = dict(zip(names, ok))
+        args.update(kw)
+        return f(*[args[k] for k in names])
+
+    assert call(B=0) == 1
+    assert call(sumM=7) == 1                 # fewer weights than filters
+    assert call(sumN=-1) == 1
+    assert call(w=None) == 1
+    assert call(w_off=None) == 1
+    assert call(n_off=None) == 1
+    assert call(r=None) == 1                 # draws requested but no output
+    assert call(ws=None) == 1
+    assert call(ws=FAKE_UNALIGNED) == 1
+    assert call(p=4) == 2
+    assert call(ws_bytes=ws - 1) == 3
 
 
 def test_profile_api_host(lib):
