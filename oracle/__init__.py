@@ -80,6 +80,10 @@ def _load():
     lib.dcro_resample_repeat.restype = i32
     lib.dcro_resample_batched.argtypes = [P, i32, P, P, i64, u64, i32, P]
     lib.dcro_resample_batched.restype = i32
+    lib.dcro_scheme_uniforms.argtypes = [i64, u64, u64, i32, P]
+    lib.dcro_scheme_uniforms.restype = i32
+    lib.dcro_resample_scheme.argtypes = [P, i32, i64, i64, u64, u64, i32, P, P, P]
+    lib.dcro_resample_scheme.restype = i32
     _lib = lib
     return lib
 
@@ -243,6 +247,39 @@ def resample(w: np.ndarray, N: int, seed: int, stream: int = 0, zkind: int | Non
         st = lib.dcro_resample(_ptr(w), M, N, seed, stream, _ptr(r), _ptr(W), _ptr(u))
     if st != OK:
         raise OracleError(f"resample: status {st}")
+    return r[:N], W, u[:N]
+
+
+# --------------------------------------------------------------------------
+# Other schemes through the same map (Sec. V): stratified and systematic
+# --------------------------------------------------------------------------
+SCHEMES = {"multinomial": 0, "stratified": 1, "systematic": 2}
+
+
+def scheme_uniforms(N: int, seed: int, stream: int = 0, scheme: str = "stratified") -> np.ndarray:
+    """Sorted uniforms of a scheme: stratified (i + v_i)/N, systematic (i + v_0)/N."""
+    u = np.empty(max(N, 1), dtype=np.float64)
+    st = _load().dcro_scheme_uniforms(N, seed, stream, SCHEMES[scheme], _ptr(u))
+    if st != OK:
+        raise OracleError(f"scheme_uniforms: status {st}")
+    return u[:N]
+
+
+def resample_scheme(w: np.ndarray, N: int, seed: int, stream: int = 0,
+                    scheme: str = "stratified"):
+    """End to end with a scheme's uniforms: returns (r, W, u)."""
+    w = np.ascontiguousarray(w)
+    is_f32 = 1 if w.dtype == np.float32 else 0
+    if not is_f32:
+        w = _f64(w)
+    M = w.shape[0]
+    r = np.empty(max(N, 1), dtype=np.int32)
+    W = np.empty(M, dtype=np.float64)
+    u = np.empty(max(N, 1), dtype=np.float64)
+    st = _load().dcro_resample_scheme(_ptr(w), is_f32, M, N, seed, stream, SCHEMES[scheme],
+                                      _ptr(r), _ptr(W), _ptr(u))
+    if st != OK:
+        raise OracleError(f"resample_scheme: status {st}")
     return r[:N], W, u[:N]
 
 

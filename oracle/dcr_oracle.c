@@ -338,6 +338,58 @@ int dcro_resample_f32(const float* w, int64_t M, int64_t N, uint64_t seed, uint6
     return resample_impl(w, 1, M, N, seed, stream, zkind, r, W_out, u_out);
 }
 
+/* ------------------------------------------------------------------------- */
+/* Other resampling schemes through the same inverse-CMF map.  Sec. V says the */
+/* divide-and-conquer map carries over to other kinds of resampling without    */
+/* giving an algorithm; the sorted uniforms here are the textbook ones:        */
+/*   stratified  u_i = (i + v_i) / N   (one variate in each stratum);          */
+/*   systematic  u_i = (i + v_0) / N   (one variate shared by all strata);     */
+/* with v_i the variate of draw i of (seed, stream) (readings R2, R3).  Both   */
+/* are non-decreasing in i and lie in (0, 1].  scheme 0 is Alg. 1.            */
+/* ------------------------------------------------------------------------- */
+#define DCRO_SCHEME_MULTINOMIAL 0
+#define DCRO_SCHEME_STRATIFIED 1
+#define DCRO_SCHEME_SYSTEMATIC 2
+
+int dcro_scheme_uniforms(int64_t N, uint64_t seed, uint64_t stream, int scheme, double* u)
+{
+    if (N < 0) return DCRO_INVALID;
+    if (scheme == DCRO_SCHEME_MULTINOMIAL) {
+        if (N > 0) dcro_sorted_uniforms(N, seed, stream, 0, u, NULL);
+        return DCRO_OK;
+    }
+    if (scheme != DCRO_SCHEME_STRATIFIED && scheme != DCRO_SCHEME_SYSTEMATIC) return DCRO_INVALID;
+    const double v0 = dcro_uniform_open(seed, stream, 0);
+    for (int64_t i = 0; i < N; ++i) {
+        const double v = (scheme == DCRO_SCHEME_STRATIFIED) ? dcro_uniform_open(seed, stream, (uint64_t)i)
+                                                           : v0;
+        u[i] = ((double)i + v) / (double)N;
+    }
+    return DCRO_OK;
+}
+
+/* End to end with the scheme's uniforms (binary32 weights promoted exactly;
+ * the multinomial scheme uses the binary32 spacings for them, as
+ * dcro_resample_f32 with zkind 1). */
+int dcro_resample_scheme(const void* w, int is_f32, int64_t M, int64_t N, uint64_t seed,
+                         uint64_t stream, int scheme, int32_t* r, double* W_out, double* u_out)
+{
+    if (M < 1 || N < 0) return DCRO_INVALID;
+    if (scheme == DCRO_SCHEME_MULTINOMIAL)
+        return resample_impl(w, is_f32, M, N, seed, stream, is_f32 ? 1 : 0, r, W_out, u_out);
+    if (scheme != DCRO_SCHEME_STRATIFIED && scheme != DCRO_SCHEME_SYSTEMATIC) return DCRO_INVALID;
+    double* W = W_out ? W_out : (double*)malloc(sizeof(double) * (size_t)M);
+    double* u = u_out ? u_out : (double*)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1));
+    int st = cumulative_weights_impl(w, is_f32, M, W, NULL);
+    if (st == DCRO_OK && N > 0) {
+        dcro_scheme_uniforms(N, seed, stream, scheme, u);
+        dcro_dac(W, M, u, N, r, NULL, NULL, 0);
+    }
+    if (!W_out) free(W);
+    if (!u_out) free(u);
+    return st;
+}
+
 /* Many independent resamples of one distribution with consecutive seeds, for
  * the statistical tests: r is [R][N]. */
 int dcro_resample_repeat(const double* w, int64_t M, int64_t N, uint64_t seed0, int64_t R,

@@ -26,7 +26,8 @@ def compile_flags() -> list[str]:
     return [
         f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
         "-ffp-contract=off",
-        # packed binary32 vector ops stay off (see the design notes)
+        # packed binary32 vector ops stay off: some of their forms have given
+        # wrong results on this chip
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         "-I", INCLUDE, "-I", CSRC,
     ]
