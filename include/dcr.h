@@ -64,6 +64,20 @@ typedef enum dcr_precision {
     DCR_FP32_COMP = 1
 } dcr_precision;
 
+/* Sorted-uniform scheme of an end-to-end call.
+ *   DCR_MULTINOMIAL: Sec. II, Alg. 1 (exponential spacings): multinomial
+ *                    resampling, the paper's case.
+ *   DCR_STRATIFIED:  u_i = (i + v_i) / N, one variate per stratum.
+ *   DCR_SYSTEMATIC:  u_i = (i + v_0) / N, one variate for all strata.
+ * v_d is the open-interval variate of draw d of (seed, stream_id), the same
+ * Philox4x32-10 draw the spacings use.  Sec. V names the extension of the
+ * divide-and-conquer map to such schemes; the map is unchanged. */
+typedef enum dcr_scheme {
+    DCR_MULTINOMIAL = 0,
+    DCR_STRATIFIED = 1,
+    DCR_SYSTEMATIC = 2
+} dcr_scheme;
+
 /* Human-readable name of a status code (static string, never NULL). */
 const char* dcr_status_string(dcr_status s);
 
@@ -152,6 +166,24 @@ dcr_status dcr_resample_batched(const void* w, const int64_t* w_off, const int64
                                 dcr_precision p, int32_t* r, int32_t* seg_status,
                                 int32_t* dev_status, void* ws, size_t ws_bytes,
                                 hipStream_t stream);
+
+/* End to end with a chosen scheme (Sec. V): as dcr_resample, whose call is
+ * dcr_resample_scheme(..., DCR_MULTINOMIAL, ...).  The workspace of
+ * dcr_workspace_bytes(M, N, p) suffices for every scheme.  u_opt receives the
+ * scheme's uniforms.  Errors: as dcr_resample; DCR_ERR_UNSUPPORTED for an
+ * unknown scheme. */
+dcr_status dcr_resample_scheme(const void* w, int64_t M, int64_t N, uint64_t seed,
+                               uint64_t stream_id, dcr_precision p, dcr_scheme scheme, int32_t* r,
+                               double* W_opt, double* u_opt, int32_t* dev_status, void* ws,
+                               size_t ws_bytes, hipStream_t stream);
+
+/* The uniforms of the stratified or systematic scheme alone:
+ *   u        [N] binary64 out, non-decreasing, in (0, 1]; needs no workspace.
+ * Errors: DCR_ERR_INVALID_ARGUMENT (N out of range, u NULL with N > 0),
+ * DCR_ERR_UNSUPPORTED for DCR_MULTINOMIAL (use dcr_sorted_uniforms) or an
+ * unknown scheme. */
+dcr_status dcr_scheme_uniforms(int64_t N, uint64_t seed, uint64_t stream_id, dcr_scheme scheme,
+                               double* u, hipStream_t stream);
 
 /* Kernel timing for measurement (not part of the sampling contract).
  * dcr_profile_begin(cap) creates HIP events for up to `cap` kernel launches;

@@ -9,6 +9,9 @@ does, and fails loudly if the library has not been built.
 from ._binding import (  # noqa: F401
     DCR_FP32_COMP,
     DCR_FP64,
+    DCR_MULTINOMIAL,
+    DCR_STRATIFIED,
+    DCR_SYSTEMATIC,
     DcrError,
     dcr_batched_workspace_bytes,
     dcr_cumulative_weights,
@@ -17,6 +20,8 @@ from ._binding import (  # noqa: F401
     dcr_profile_end,
     dcr_resample,
     dcr_resample_batched,
+    dcr_resample_scheme,
+    dcr_scheme_uniforms,
     dcr_sorted_uniforms,
     dcr_status_string,
     dcr_workspace_bytes,

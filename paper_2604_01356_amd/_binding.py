@@ -66,6 +66,11 @@ def library():
     lib.dcr_resample_batched.argtypes = [P, P, P, i32, i64, i64, u64, ctypes.c_int, P, P, P, P,
                                          sz, P]
     lib.dcr_resample_batched.restype = ctypes.c_int
+    lib.dcr_resample_scheme.argtypes = [P, i64, i64, u64, u64, ctypes.c_int, ctypes.c_int, P, P,
+                                        P, P, P, sz, P]
+    lib.dcr_resample_scheme.restype = ctypes.c_int
+    lib.dcr_scheme_uniforms.argtypes = [i64, u64, u64, ctypes.c_int, P, P]
+    lib.dcr_scheme_uniforms.restype = ctypes.c_int
     lib.dcr_profile_begin.argtypes = [i32]
     lib.dcr_profile_begin.restype = ctypes.c_int
     lib.dcr_profile_end.argtypes = [i32, P, P]
@@ -185,6 +190,44 @@ def dcr_inverse_cmf(W, u, r=None):
     _check("dcr_inverse_cmf", library().dcr_inverse_cmf(
         _ptr(W), W.numel(), _ptr(u), N, _ptr(r), None, 0, _stream(u.device)))
     return r[:N]
+
+
+DCR_MULTINOMIAL = 0
+DCR_STRATIFIED = 1
+DCR_SYSTEMATIC = 2
+
+
+def dcr_resample_scheme(w, N: int, seed: int, stream_id: int = 0, scheme: int = DCR_MULTINOMIAL,
+                        r=None, W_out=None, u_out=None, dev_status=None, ws=None):
+    """End to end with the scheme's sorted uniforms (multinomial, stratified, systematic)."""
+    import torch
+    _dev_tensor(w, "w")
+    M = w.numel()
+    p = precision_of(w)
+    N = int(N)
+    if r is None:
+        r = torch.empty(max(N, 1), dtype=torch.int32, device=w.device)
+    _dev_tensor(r, "r", torch.int32, N)
+    _dev_tensor(W_out, "W_out", torch.float64, M)
+    _dev_tensor(u_out, "u_out", torch.float64, N)
+    _dev_tensor(dev_status, "dev_status", torch.int32, 1)
+    ws = _workspace(ws, M, N, p, w.device)
+    _check("dcr_resample_scheme", library().dcr_resample_scheme(
+        _ptr(w), M, N, int(seed), int(stream_id), p, int(scheme), _ptr(r), _ptr(W_out),
+        _ptr(u_out), _ptr(dev_status), _ptr(ws), ws.numel(), _stream(w.device)))
+    return r[:N]
+
+
+def dcr_scheme_uniforms(N: int, seed: int, stream_id: int = 0, scheme: int = DCR_STRATIFIED,
+                        u=None, device="cuda"):
+    """The stratified or systematic scheme's N sorted uniforms."""
+    import torch
+    if u is None:
+        u = torch.empty(max(int(N), 1), dtype=torch.float64, device=device)
+    _dev_tensor(u, "u", torch.float64, int(N))
+    _check("dcr_scheme_uniforms", library().dcr_scheme_uniforms(
+        int(N), int(seed), int(stream_id), int(scheme), _ptr(u), _stream(u.device)))
+    return u[: int(N)]
 
 
 def dcr_resample(w, N: int, seed: int, stream_id: int = 0, r=None, W_out=None, u_out=None,

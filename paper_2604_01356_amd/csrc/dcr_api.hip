@@ -37,8 +37,9 @@ struct Layout {
     size_t bytes = 0;
 };
 
-// Workspace layout: [header][weight side][spacing side][dense-map flags]
-Layout make_layout(int64_t M, int64_t N) {
+// Workspace layout: [header][weight side][spacing side][dense-map flags];
+// the stratified and systematic schemes have no spacing side.
+Layout make_layout(int64_t M, int64_t N, int scheme = dcr::kSchemeMultinomial) {
     Layout L;
     size_t off = 0;
     L.status = off;
@@ -54,7 +55,7 @@ Layout make_layout(int64_t M, int64_t N) {
         L.w_sub = off;
         off = align256(off + sizeof(double) * L.nwb * kWSubPerBlock);
     }
-    if (N > 0) {
+    if (N > 0 && scheme == dcr::kSchemeMultinomial) {
         L.nzb = (N + 1 + kZBlock - 1) / kZBlock;
         L.z_tot = off;
         off = align256(off + sizeof(double) * L.nzb);
@@ -62,6 +63,8 @@ Layout make_layout(int64_t M, int64_t N) {
         off = align256(off + sizeof(double) * L.nzb);
         L.z_buf = off;
         off = align256(off + sizeof(double) * L.nzb * kZBlock);
+    }
+    if (N > 0) {
         L.wide = off;
         off = align256(off + sizeof(int32_t) * ((N + kDenseU - 1) / kDenseU));
     }
@@ -88,12 +91,14 @@ WArgs w_args(const Layout& L, void* ws, int64_t M) {
     return a;
 }
 
-ZArgs z_args(const Layout& L, void* ws, int64_t N, uint64_t seed, uint64_t stream) {
+ZArgs z_args(const Layout& L, void* ws, int64_t N, uint64_t seed, uint64_t stream,
+             int scheme = dcr::kSchemeMultinomial) {
     ZArgs a{};
     a.N = N;
     a.nb = L.nzb;
     a.seed = seed;
     a.stream = stream;
+    a.scheme = scheme;
     a.zrel = at<double>(ws, L.z_buf);
     a.blk_tot = at<double>(ws, L.z_tot);
     a.beta = at<double>(ws, L.z_beta);
@@ -233,17 +238,43 @@ dcr_status dcr_inverse_cmf(const double* W, int64_t M, const double* u, int64_t 
     return hip_status(e);
 }
 
+static bool valid_scheme(dcr_scheme s) {
+    return s == DCR_MULTINOMIAL || s == DCR_STRATIFIED || s == DCR_SYSTEMATIC;
+}
+
+dcr_status dcr_scheme_uniforms(int64_t N, uint64_t seed, uint64_t stream_id, dcr_scheme scheme,
+                               double* u, hipStream_t stream) {
+    if (N < 0 || N > kMaxN) return DCR_ERR_INVALID_ARGUMENT;
+    if (scheme != DCR_STRATIFIED && scheme != DCR_SYSTEMATIC) return DCR_ERR_UNSUPPORTED;
+    if (N == 0) return DCR_OK;
+    if (!u) return DCR_ERR_INVALID_ARGUMENT;
+    const Layout L = make_layout(0, N, scheme);
+    const ZArgs za = z_args(L, nullptr, N, seed, stream_id, scheme);
+    const SharedArgs sh{};
+    const hipError_t e =
+        timed(kKMatU, stream, [&] { return dcr::launch_materialize_u(za, sh, u, stream); });
+    return hip_status(e);
+}
+
 dcr_status dcr_resample(const void* w, int64_t M, int64_t N, uint64_t seed, uint64_t stream_id,
                         dcr_precision p, int32_t* r, double* W_opt, double* u_opt,
                         int32_t* dev_status, void* ws, size_t ws_bytes, hipStream_t stream) {
+    return dcr_resample_scheme(w, M, N, seed, stream_id, p, DCR_MULTINOMIAL, r, W_opt, u_opt,
+                               dev_status, ws, ws_bytes, stream);
+}
+
+dcr_status dcr_resample_scheme(const void* w, int64_t M, int64_t N, uint64_t seed,
+                               uint64_t stream_id, dcr_precision p, dcr_scheme scheme, int32_t* r,
+                               double* W_opt, double* u_opt, int32_t* dev_status, void* ws,
+                               size_t ws_bytes, hipStream_t stream) {
     if (M < 1 || M > kMaxM || N < 0 || N > kMaxN || !w || !ws) return DCR_ERR_INVALID_ARGUMENT;
     if (N > 0 && !r) return DCR_ERR_INVALID_ARGUMENT;
-    if (!valid_prec(p)) return DCR_ERR_UNSUPPORTED;
+    if (!valid_prec(p) || !valid_scheme(scheme)) return DCR_ERR_UNSUPPORTED;
     if ((reinterpret_cast<uintptr_t>(ws) & 255u) != 0) return DCR_ERR_INVALID_ARGUMENT;
-    const Layout L = make_layout(M, N);
+    const Layout L = make_layout(M, N, scheme);
     if (ws_bytes < L.bytes) return DCR_ERR_WORKSPACE_TOO_SMALL;
     const WArgs wa = w_args(L, ws, M);
-    const ZArgs za = z_args(L, ws, N, seed, stream_id);
+    const ZArgs za = z_args(L, ws, N, seed, stream_id, scheme);
     const SharedArgs sh = shared_args(L, ws);
     const int prec = prec_code(p);
     const int vec = (aligned16(w) ? 1 : 0) | (aligned16(W_opt) ? 2 : 0);

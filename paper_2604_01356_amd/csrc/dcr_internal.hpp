@@ -32,12 +32,20 @@ struct WArgs {
     double* sub_end;   // [nb*128] in-block sub-tile ends sigma_1..sigma_128
 };
 
-// Spacing side: draws 0..N in nb blocks of 4096.
+// Sorted-uniform schemes: Alg. 1 (exponential spacings), stratified
+// (i + v_i) / N and systematic (i + v_0) / N.
+constexpr int kSchemeMultinomial = 0;
+constexpr int kSchemeStratified = 1;
+constexpr int kSchemeSystematic = 2;
+
+// Spacing side: draws 0..N in nb blocks of 4096 (nb = 0 for the stratified
+// and systematic schemes, whose uniforms need no scan).
 struct ZArgs {
     int64_t N;
     int64_t nb;
     uint64_t seed;
     uint64_t stream;
+    int32_t scheme;
     double* zrel;      // [N+1] in-block prefix sums of the spacings
     double* blk_tot;   // [nb]
     double* beta;      // [nb]
@@ -99,7 +107,7 @@ struct BatchArgs {
     int64_t sumM_cap, sumN_cap;
     int64_t* wt_base;       // [B+1] first weight block of each filter (k_batch_plan)
     int64_t* zt_base;       // [B+1] first spacing block
-    int64_t* mc_base;       // [B+1] first map chunk (64 draws)
+    int64_t* mc_base;       // [B+1] first map chunk (1024 draws)
     int32_t* head;          // [0] plan status, [1] batch status
     double* wt_tot;         // [wt_cap] weight-block totals
     double* wt_beta;        // [wt_cap] weight-block ends (per filter)
@@ -113,7 +121,7 @@ struct BatchArgs {
 constexpr int kPlanThreads = 1024;
 constexpr int64_t kBatchWBlock = 32768;
 constexpr int64_t kBatchZBlock = 4096;
-constexpr int64_t kBatchChunk = 64;
+constexpr int64_t kBatchChunk = 1024;
 // The batched launches, in order: plan, reduce, carries, map.
 hipError_t launch_batch_plan(const BatchArgs& ba, int32_t* dev_status, hipStream_t s);
 hipError_t launch_reduce_batched(int prec, const void* w, const BatchArgs& ba, hipStream_t s);

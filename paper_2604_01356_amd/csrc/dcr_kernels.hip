@@ -11,7 +11,11 @@
 //                       implicit (block bases + sub-tile bases + a rescan of one
 //                       256-weight sub-tile), the divide-and-conquer map of
 //                       Alg. 5 laid onto the block / sub-tile / element levels
+//   k_map_dense         inverse CMF when N >= M/4: the linear merge of Alg. 4
+//   k_map_wide          the chunks k_map_dense leaves (spans too wide to merge)
 //   k_map_w             inverse CMF against a given W (stage 3 alone)
+//   k_batch_plan, k_reduce_batched, k_carries_batched, k_map_batched
+//                       the batched form: many filters in one call
 // The summation structure that fixes the bits of W and u is described in
 // dcr_device.hpp.
 #include <hip/hip_ext.h>
@@ -429,10 +433,26 @@ __device__ __forceinline__ double uniform_of(double zrel, int64_t i, int64_t N, 
     return Z / ztot;
 }
 
+// Uniform i of the stratified, (i + v_i) / N, or systematic, (i + v_0) / N,
+// scheme, with v_d the open-interval variate of draw d of (seed, stream).
+__device__ __forceinline__ double scheme_uniform(const ZArgs& za, int64_t i) {
+    const uint64_t d = (za.scheme == kSchemeSystematic) ? 0 : static_cast<uint64_t>(i);
+    const uint64_t pair = d >> 1;
+    const Words4 x = philox4x32_10(static_cast<uint32_t>(pair), static_cast<uint32_t>(pair >> 32),
+                                   static_cast<uint32_t>(za.stream),
+                                   static_cast<uint32_t>(za.stream >> 32),
+                                   static_cast<uint32_t>(za.seed),
+                                   static_cast<uint32_t>(za.seed >> 32));
+    const double v = (d & 1) ? variate_from_words(x.w2, x.w3) : variate_from_words(x.w0, x.w1);
+    return (static_cast<double>(i) + v) / static_cast<double>(za.N);
+}
+
 // Uniform i formed from the stored in-block spacing prefix and the scanned
-// spacing-block ends (the same values k_materialize_u writes).
+// spacing-block ends (the same values k_materialize_u writes), or by the
+// scheme's formula.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double uniform_at(const ZArgs& za, double ztot, int64_t i) {
+    if (za.scheme != kSchemeMultinomial) return scheme_uniform(za, i);
     const int64_t g = i / kZBlock;
     const double beta_g = (g == 0) ? 0.0 : za.beta[g - 1];
     return uniform_of(za.zrel[i], i, za.N, beta_g, za.beta[g], ztot);
@@ -541,6 +561,15 @@ __global__ __launch_bounds__(kThreads) void k_materialize_w(const Tin* __restric
 __global__ __launch_bounds__(kThreads) void k_materialize_u(ZArgs za, SharedArgs sh,
                                                             double* __restrict__ u, int vec_out) {
     const int64_t g = blockIdx.x;
+    if (za.scheme != kSchemeMultinomial) {
+        const int64_t j0 = g * kZBlock + static_cast<int64_t>(threadIdx.x) * kLane;
+        const int nj = clamp_count(za.N - j0, kLane);
+        double o[kLane];
+#pragma unroll
+        for (int k = 0; k < kLane; ++k) o[k] = (k < nj) ? scheme_uniform(za, j0 + k) : 0.0;
+        store_uniforms(u, j0, nj, o, vec_out);
+        return;
+    }
     const double beta_g = (g == 0) ? 0.0 : za.beta[g - 1];
     const double beta_n = za.beta[g];
     const double ztot = sh.totals[1];
@@ -841,7 +870,10 @@ __global__ __launch_bounds__(kThreads) void k_map_dense(const Tin* __restrict__ 
     // this thread's 16 draws lie in one spacing block (16 divides 4096): load
     // their in-block prefixes at once, then form the uniforms
     double us[kDensePer];
-    if (nmine == kDensePer) {
+    if (za.scheme != kSchemeMultinomial) {
+#pragma unroll
+        for (int q = 0; q < kDensePer; ++q) us[q] = 0.0;
+    } else if (nmine == kDensePer) {
         const f64x2* q2 = reinterpret_cast<const f64x2*>(za.zrel + iu0);
 #pragma unroll
         for (int v = 0; v < kDensePer / 2; ++v) {
@@ -854,10 +886,16 @@ __global__ __launch_bounds__(kThreads) void k_map_dense(const Tin* __restrict__ 
         for (int q = 0; q < kDensePer; ++q) us[q] = (q < nmine) ? za.zrel[iu0 + q] : 0.0;
     }
     const int64_t gz = iu0 / kZBlock;
-    const double zb = (gz == 0) ? 0.0 : za.beta[gz - 1];
-    const double zn = za.beta[gz < za.nb ? gz : za.nb - 1];
+    const bool spacings = za.scheme == kSchemeMultinomial;
+    const double zb = (!spacings || gz == 0) ? 0.0 : za.beta[gz - 1];
+    const double zn = spacings ? za.beta[gz < za.nb ? gz : za.nb - 1] : 0.0;
+    if (za.scheme != kSchemeMultinomial) {
 #pragma unroll
-    for (int q = 0; q < kDensePer; ++q) us[q] = uniform_of(us[q], iu0 + q, N, zb, zn, ztot);
+        for (int q = 0; q < kDensePer; ++q) us[q] = (q < nmine) ? scheme_uniform(za, iu0 + q) : 0.0;
+    } else {
+#pragma unroll
+        for (int q = 0; q < kDensePer; ++q) us[q] = uniform_of(us[q], iu0 + q, N, zb, zn, ztot);
+    }
     if (u_out) store_uniforms(u_out, iu0, nmine, us, (reinterpret_cast<uintptr_t>(u_out) & 15) == 0);
     if (nmine > 0 && t * kDensePer == 0) uends[0] = us[0];
 #pragma unroll
@@ -1018,7 +1056,8 @@ __global__ __launch_bounds__(kThreads) void k_finish(const Tin* __restrict__ w, 
     ScanIn si[2];
     scan_load(wa.blk_tot, wa.nb, si[0]);
     scan_load(za.blk_tot, za.nb, si[1]);
-    const double zrel = (i < za.N) ? za.zrel[i] : 0.0;
+    const bool spacings = za.scheme == kSchemeMultinomial;
+    const double zrel = (spacings && i < za.N) ? za.zrel[i] : 0.0;
     const ScanOut so[2] = {{wa.blk_tot, wa.nb, sbeta, lead ? wa.beta : nullptr},
                            {za.blk_tot, za.nb, szbeta, lead ? za.beta : nullptr}};
     double tt[2];
@@ -1035,7 +1074,9 @@ __global__ __launch_bounds__(kThreads) void k_finish(const Tin* __restrict__ w, 
     }
     if (i >= za.N) return;   // the four lanes of a quad share i
     const int64_t g = i / kZBlock;
-    const double uu = uniform_of(zrel, i, za.N, (g == 0) ? 0.0 : szbeta[g - 1], szbeta[g], ztot);
+    const double uu = spacings ? uniform_of(zrel, i, za.N, (g == 0) ? 0.0 : szbeta[g - 1],
+                                            szbeta[g], ztot)
+                               : scheme_uniform(za, i);
     if (u_out && qi == 0) u_out[i] = uu;
     if (status != kStatusOk) {
         if (qi == 0) r[i] = -1;
@@ -1085,7 +1126,6 @@ __global__ __launch_bounds__(kThreads) void k_map_w(const double* __restrict__ W
 // filter by a search of those bases.  Each then runs the single-distribution
 // block code on the filter's own view of the arrays.
 // ---------------------------------------------------------------------------
-static_assert(kBatchChunk == kUPerWG, "a map chunk is one workgroup of quads");
 static_assert(kBatchWBlock == kWBlock && kBatchZBlock == kZBlock, "block sizes");
 constexpr int kStatusInvalid = 1;
 constexpr int kStatusCapacity = 4;
@@ -1193,6 +1233,7 @@ __device__ __forceinline__ ZArgs seg_zargs(const BatchArgs& ba, int b) {
     a.nb = ba.zt_base[b + 1] - t0;
     a.seed = ba.seed;
     a.stream = static_cast<uint64_t>(b);
+    a.scheme = kSchemeMultinomial;
     a.zrel = ba.zrel + ba.n_off[b] + b;
     a.blk_tot = ba.zt_tot + t0;
     a.beta = ba.zt_beta + t0;
@@ -1244,12 +1285,341 @@ __global__ __launch_bounds__(kScanThreads) void k_carries_batched(BatchArgs ba) 
     if (threadIdx.x == 0 && sh.status[0] != kStatusOk) atomicMax(ba.head + 1, kStatusBadWeights);
 }
 
-// 64 draws of one filter per workgroup; indices are local to the filter.
+// ---------------------------------------------------------------------------
+// Map of a chunk of kSegU consecutive draws with the sub-tiles shared between
+// draws (the batched filters draw on average one index per 40 weights, and
+// several draws fall in most touched sub-tiles).  The divide-and-conquer
+// levels of Alg. 5, per workgroup:
+//   block     every draw's block by a search of the block ends in LDS;
+//   sub-tile  the sub-tile ends of the chunk's blocks staged in LDS once,
+//             then a search per draw (a global search when the chunk spans
+//             more blocks than the stage holds);
+//   split     the distinct sub-tiles are compacted in draw order;
+//   chunk     the 16 lane-chunk totals of every touched sub-tile (one load
+//             per chunk, all in flight together), their left-to-right running
+//             sums, then a search of the 16 chunk ends per draw;
+//   element   each draw re-reads its chunk's 16 weights (just fetched, so
+//             from cache) and counts the partial sums below its threshold.
+// Comparisons are of unnormalised partial sums S_j with the threshold x of
+// each draw (S_j >= x  <=>  W_j >= u).  Sums follow k_reduce's order.
+// ---------------------------------------------------------------------------
+constexpr int kSegU = 1024;                  // draws per workgroup
+constexpr int kSegPer = kSegU / kThreads;
+constexpr int kSegBetaLds = 512;             // block ends kept in LDS (sampled beyond)
+constexpr int kSegSubBlocks = 8;             // blocks whose sub-tile ends are staged
+constexpr int kSegPass = 128;                // touched sub-tiles per chunk pass
+constexpr int kSegDraws = 3;                 // draws per thread in flight at the element level
+static_assert(kBatchChunk == kSegU, "a map chunk is the draws of one k_map_batched workgroup");
+
+struct SegLds {
+    double sx[kSegU];                                  // thresholds, in draw order
+    double sbeta[kSegBetaLds];
+    double ssub[kSegSubBlocks * kWSubPerBlock];
+    double crun[kSegPass * kRowLanes];                 // chunk totals, then running sums
+    int32_t sid[kSegU];                                // sub-tile of each draw, then r
+    int16_t srank[kSegU];                              // rank of each draw's sub-tile
+    int32_t lsub[kSegU];                               // touched sub-tiles
+    int32_t lstart[kSegU + 1];                         // first draw of each
+    int32_t wsum[kThreads / 64];
+    int32_t span[2];
+};
+
+// First block b (0..nb-1) with beta_b >= x (beta_b = end of block b).
+__device__ __forceinline__ int64_t seg_block_of(const WArgs& wa, const double* sbeta, int64_t kstride,
+                                                int ns, double x) {
+    int lo = 0, hi = ns - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (sbeta[mid] < x)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    int64_t blo = static_cast<int64_t>(lo) * kstride;
+    int64_t bhi = ((static_cast<int64_t>(lo) + 1) * kstride < wa.nb ? (lo + 1) * kstride : wa.nb) - 1;
+    while (blo < bhi) {
+        const int64_t mid = (blo + bhi) >> 1;
+        if (wa.beta[mid] < x)
+            blo = mid + 1;
+        else
+            bhi = mid;
+    }
+    return blo;
+}
+
+// The same kept unconverted in registers (binary32 stays 4 bytes a value).
+template <typename Tin>
+__device__ __forceinline__ RawChunk<Tin> seg_load_raw(const Tin* __restrict__ p, int n) {
+    if (n == kLane) return load_raw_any<Tin>(p);
+    RawChunk<Tin> rc;
+    constexpr int kPer = (sizeof(Tin) == 4) ? 4 : 2;
+#pragma unroll
+    for (int q = 0; q < kLane; ++q) rc.v[q / kPer][q % kPer] = (q < n) ? p[q] : static_cast<Tin>(0);
+    return rc;
+}
+
+template <typename Tin>
+__device__ void map_seg_chunk(const Tin* __restrict__ w, const WArgs& wa, const ZArgs& za,
+                              const SharedArgs& sh, int32_t* __restrict__ r, int64_t c, SegLds& L) {
+    const int t = threadIdx.x;
+    const int64_t N = za.N;
+    const int64_t i0 = c * kSegU;
+    const int nu = static_cast<int>((N - i0 < kSegU) ? N - i0 : kSegU);
+    const bool ok = sh.status[0] == kStatusOk;
+    if (!ok) {
+        for (int k = 0; k < kSegPer; ++k) {
+            const int pos = t + k * kThreads;
+            if (pos < nu) r[i0 + pos] = -1;
+        }
+        return;
+    }
+    const double total = sh.totals[0];
+    const double ztot = sh.totals[1];
+    const int64_t nb = wa.nb;
+    const int64_t kstride = (nb + kSegBetaLds - 1) / kSegBetaLds;
+    const int ns = static_cast<int>((nb + kstride - 1) / kstride);
+    for (int q = t; q < ns; q += kThreads) {
+        const int64_t b = (static_cast<int64_t>(q) + 1) * kstride - 1;
+        L.sbeta[q] = wa.beta[b < nb ? b : nb - 1];
+    }
+    // block end beta_b and the previous end, from LDS when every end is there
+    auto beta_end = [&](int64_t b) { return (kstride == 1) ? L.sbeta[b] : wa.beta[b]; };
+    // ---- thresholds of the chunk's draws (coalesced: position t + 256k) ----
+    double xs[kSegPer];
+#pragma unroll
+    for (int k = 0; k < kSegPer; ++k) {
+        const int pos = t + k * kThreads;
+        xs[k] = __builtin_huge_val();
+        if (pos < nu) xs[k] = threshold_for(uniform_at(za, ztot, i0 + pos), total);
+        L.sx[pos] = xs[k];
+    }
+    lds_barrier();
+    // ---- block level, and the blocks spanned by the chunk ----
+    int64_t bk[kSegPer];
+    if (kstride == 1) {
+        // count of block ends below x among the first ns-1, for the draws in
+        // lock step (the last end is the total, never below x)
+        int cnt[kSegPer] = {};
+        for (int step = kSegBetaLds / 2; step >= 1; step >>= 1) {
+#pragma unroll
+            for (int k = 0; k < kSegPer; ++k)
+                if (cnt[k] + step <= ns - 1 && L.sbeta[cnt[k] + step - 1] < xs[k]) cnt[k] += step;
+        }
+#pragma unroll
+        for (int k = 0; k < kSegPer; ++k) bk[k] = cnt[k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < kSegPer; ++k)
+            bk[k] = (t + k * kThreads < nu) ? seg_block_of(wa, L.sbeta, kstride, ns, xs[k]) : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < kSegPer; ++k) {
+        const int pos = t + k * kThreads;
+        if (pos >= nu) bk[k] = 0;
+        if (pos == 0) L.span[0] = static_cast<int32_t>(bk[k]);
+        if (pos == nu - 1) L.span[1] = static_cast<int32_t>(bk[k]);
+    }
+    lds_barrier();
+    const int64_t bfirst = L.span[0], blast = L.span[1];
+    const bool staged = blast - bfirst + 1 <= kSegSubBlocks;
+    if (staged) {
+        const int64_t n = (blast - bfirst + 1) * kWSubPerBlock;
+        const double* src = wa.sub_end + bfirst * kWSubPerBlock;
+        for (int q = t; q < n; q += kThreads) L.ssub[q] = src[q];
+    }
+    lds_barrier();
+    // sigma_s of block b (stored end of sub-tile s-1; 0 for s = 0)
+    auto sigma_of = [&](int64_t b, int s) {
+        if (s == 0) return 0.0;
+        return staged ? L.ssub[(b - bfirst) * kWSubPerBlock + s - 1]
+                      : wa.sub_end[b * kWSubPerBlock + s - 1];
+    };
+    // ---- sub-tile level: first s with end(s) >= x, where
+    //      end(s) = min(beta_{b-1} + sigma_{s+1}, beta_b), end(nsub-1) = beta_b ----
+    {
+        double bb[kSegPer], bn[kSegPer];
+        int nsub[kSegPer], cnt[kSegPer];
+#pragma unroll
+        for (int k = 0; k < kSegPer; ++k) {
+            // unused positions search the first staged block (in range)
+            if (t + k * kThreads >= nu) bk[k] = bfirst;
+            const int64_t b = bk[k];
+            bb[k] = (b == 0) ? 0.0 : beta_end(b - 1);
+            bn[k] = beta_end(b);
+            const int64_t blen = (wa.M - b * kWBlock < kWBlock) ? wa.M - b * kWBlock : kWBlock;
+            nsub[k] = static_cast<int>((blen + kSub - 1) / kSub);
+            cnt[k] = 0;
+        }
+        // count of sub-tile ends below x among the first nsub-1, in lock step
+        for (int step = kWSubPerBlock / 2; step >= 1; step >>= 1) {
+#pragma unroll
+            for (int k = 0; k < kSegPer; ++k)
+                if (cnt[k] + step <= nsub[k] - 1 &&
+                    fmin(bb[k] + sigma_of(bk[k], cnt[k] + step), bn[k]) < xs[k])
+                    cnt[k] += step;
+        }
+#pragma unroll
+        for (int k = 0; k < kSegPer; ++k) {
+            const int pos = t + k * kThreads;
+            if (pos < nu) L.sid[pos] = static_cast<int32_t>(bk[k] * kWSubPerBlock + cnt[k]);
+        }
+    }
+    lds_barrier();
+    // ---- split: distinct sub-tiles in draw order (thread t owns positions
+    //      4t..4t+3) ----
+    int heads = 0;
+    int hmask = 0;
+#pragma unroll
+    for (int k = 0; k < kSegPer; ++k) {
+        const int pos = kSegPer * t + k;
+        const bool h = pos < nu && (pos == 0 || L.sid[pos] != L.sid[pos - 1]);
+        hmask |= h ? (1 << k) : 0;
+        heads += h ? 1 : 0;
+    }
+    const int lane64 = t & 63;
+    int incl = heads;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int v = __shfl_up(incl, d, 64);
+        if (lane64 >= d) incl += v;
+    }
+    if (lane64 == 63) L.wsum[t >> 6] = incl;
+    lds_barrier();
+    int wbase = 0;
+    for (int q = 0; q < (t >> 6); ++q) wbase += L.wsum[q];
+    const int ntouched = L.wsum[0] + L.wsum[1] + L.wsum[2] + L.wsum[3];
+    int rank = wbase + incl - heads - 1;
+#pragma unroll
+    for (int k = 0; k < kSegPer; ++k) {
+        const int pos = kSegPer * t + k;
+        if (hmask & (1 << k)) {
+            ++rank;
+            L.lsub[rank] = L.sid[pos];
+            L.lstart[rank] = pos;
+        }
+        if (pos < nu) L.srank[pos] = static_cast<int16_t>(rank);
+    }
+    if (t == 0) L.lstart[ntouched] = nu;
+    lds_barrier();
+    // ---- chunk and element levels, kSegPass touched sub-tiles at a time ----
+    const int row = t / kRowLanes;
+    const int lane = t % kRowLanes;
+    for (int p0 = 0; p0 < ntouched; p0 += kSegPass) {
+        const int p1 = (p0 + kSegPass < ntouched) ? p0 + kSegPass : ntouched;
+        // chunk totals: thread (row, lane) sums chunk `lane` of sub-tiles p0+row+16m
+#pragma unroll 4
+        for (int k = p0 + row; k < p1; k += kRows) {
+            const int32_t g = L.lsub[k];
+            const int64_t b = g / kWSubPerBlock;
+            const int64_t j0 = b * kWBlock + static_cast<int64_t>(g % kWSubPerBlock) * kSub +
+                               lane * kLane;
+            const int nv = clamp_count(wa.M - j0, kLane);
+            const int64_t bend = b * kWBlock + kWBlock;
+            const int nvb = (j0 + nv <= bend) ? nv : static_cast<int>(bend - j0);
+            const RawChunk<Tin> rc = seg_load_raw<Tin>(w + (nvb > 0 ? j0 : 0), nvb > 0 ? nvb : 0);
+            // left to right from the first value, as k_reduce sums a chunk
+            double cs = rc.at(0);
+#pragma unroll
+            for (int q = 1; q < kLane; ++q) cs = cs + rc.at(q);
+            L.crun[(k - p0) * kRowLanes + lane] = cs;
+        }
+        lds_barrier();
+        // running sums c_{l+1} = c_l + t_l, left to right
+        if (t < p1 - p0) {
+            double run = 0.0;
+#pragma unroll
+            for (int l = 0; l < kRowLanes; ++l) {
+                run = run + L.crun[t * kRowLanes + l];
+                L.crun[t * kRowLanes + l] = run;
+            }
+        }
+        lds_barrier();
+        // draws of these sub-tiles, kSegDraws per thread at a time: chunk
+        // searches in lock step, then all chunk loads, then the counts
+        const int d0 = L.lstart[p0], d1 = L.lstart[p1];
+        for (int pb = d0; pb < d1; pb += kSegDraws * kThreads) {
+            int lc[kSegDraws], nv[kSegDraws], nl[kSegDraws];
+            int64_t j0[kSegDraws];
+            double bb[kSegDraws], bn[kSegDraws], sg[kSegDraws], cl[kSegDraws], xx[kSegDraws];
+            bool eb[kSegDraws];
+            const double* cr[kSegDraws];
+#pragma unroll
+            for (int m = 0; m < kSegDraws; ++m) {
+                const int pos = pb + t + m * kThreads;
+                const bool v = pos < d1;
+                const int k = v ? L.srank[pos] : p0;
+                const int32_t g = L.lsub[k];
+                const int64_t b = g / kWSubPerBlock;
+                const int s = g % kWSubPerBlock;
+                xx[m] = v ? L.sx[pos] : -__builtin_huge_val();
+                const int64_t blk0 = b * kWBlock;
+                const int64_t jlast = ((blk0 + kWBlock < wa.M) ? blk0 + kWBlock : wa.M) - 1;
+                const int64_t sub0 = blk0 + static_cast<int64_t>(s) * kSub;
+                const int slen = static_cast<int>((jlast - sub0 + 1 < kSub) ? jlast - sub0 + 1 : kSub);
+                nl[m] = (slen + kLane - 1) / kLane;
+                bb[m] = (b == 0) ? 0.0 : beta_end(b - 1);
+                bn[m] = beta_end(b);
+                sg[m] = sigma_of(b, s);
+                eb[m] = sub0 + slen - 1 == jlast;
+                cr[m] = L.crun + (k - p0) * kRowLanes;
+                j0[m] = sub0;
+                nv[m] = slen;
+                lc[m] = 0;
+            }
+            // first chunk whose end reaches x (the last chunk's end is end(s) >= x)
+#pragma unroll
+            for (int step = kRowLanes / 2; step >= 1; step >>= 1) {
+#pragma unroll
+                for (int m = 0; m < kSegDraws; ++m)
+                    if (lc[m] + step <= nl[m] - 1 &&
+                        fmin(bb[m] + (sg[m] + cr[m][lc[m] + step - 1]), bn[m]) < xx[m])
+                        lc[m] += step;
+            }
+            RawChunk<Tin> xv[kSegDraws];
+#pragma unroll
+            for (int m = 0; m < kSegDraws; ++m) {
+                cl[m] = (lc[m] == 0) ? 0.0 : cr[m][lc[m] - 1];
+                const int slen = nv[m];
+                nv[m] = (pb + t + m * kThreads < d1)
+                            ? ((slen - lc[m] * kLane < kLane) ? slen - lc[m] * kLane : kLane)
+                            : 0;
+                j0[m] += lc[m] * kLane;
+                xv[m] = seg_load_raw<Tin>(w + (nv[m] > 0 ? j0[m] : 0), nv[m]);
+            }
+#pragma unroll
+            for (int m = 0; m < kSegDraws; ++m) {
+                const int pos = pb + t + m * kThreads;
+                if (pos >= d1) continue;
+                const bool last = eb[m] && lc[m] == nl[m] - 1;
+                double pk = 0.0;
+                int cnt = 0;
+#pragma unroll
+                for (int q = 0; q < kLane; ++q) {
+                    pk = pk + xv[m].at(q);
+                    const double S = (last && q == nv[m] - 1)
+                                         ? bn[m]
+                                         : fmin(bb[m] + (sg[m] + (cl[m] + pk)), bn[m]);
+                    cnt += (q < nv[m] && S < xx[m]) ? 1 : 0;
+                }
+                L.sid[pos] = static_cast<int32_t>(j0[m] + cnt);
+            }
+        }
+        lds_barrier();   // crun is rewritten by the next pass
+    }
+    // ---- coalesced index store ----
+#pragma unroll
+    for (int k = 0; k < kSegPer; ++k) {
+        const int pos = t + k * kThreads;
+        if (pos < nu) r[i0 + pos] = L.sid[pos];
+    }
+}
+
+// kSegU draws of one filter per workgroup; indices are local to the filter.
 template <typename Tin>
 __global__ __launch_bounds__(kThreads) void k_map_batched(const Tin* __restrict__ w, BatchArgs ba,
                                                           int32_t* __restrict__ r,
                                                           int32_t* dev_status) {
-    __shared__ double sbeta[kBetaLds];
+    __shared__ SegLds L;
     const int plan = ba.head[0];
     if (blockIdx.x == 0 && threadIdx.x == 0 && dev_status)
         *dev_status = (plan != kStatusOk) ? plan : ba.head[1];
@@ -1258,8 +1628,8 @@ __global__ __launch_bounds__(kThreads) void k_map_batched(const Tin* __restrict_
     if (c >= ba.mc_base[ba.B]) return;
     const int b = find_segment(ba.mc_base, ba.B, c);
     const Tin* ws = w + ba.w_off[b];
-    map_chunk<Tin>(ws, seg_wargs(ba, b), seg_zargs(ba, b), seg_shared(ba, b), nullptr,
-                   r + ba.n_off[b], aligned16_flag(ws), c - ba.mc_base[b], sbeta);
+    map_seg_chunk<Tin>(ws, seg_wargs(ba, b), seg_zargs(ba, b), seg_shared(ba, b),
+                       r + ba.n_off[b], c - ba.mc_base[b], L);
 }
 
 // ---------------------------------------------------------------------------
@@ -1311,10 +1681,12 @@ hipError_t launch_materialize_w(int prec, const void* w, const WArgs& wa, const 
 }
 
 hipError_t launch_materialize_u(const ZArgs& za, const SharedArgs& sh, double* u, hipStream_t s) {
-    if (za.nb <= 0 || za.N <= 0) return hipSuccess;
+    if (za.N <= 0) return hipSuccess;
+    const int64_t grid = (za.scheme != kSchemeMultinomial) ? (za.N + kZBlock - 1) / kZBlock : za.nb;
+    if (grid <= 0) return hipSuccess;
     const int vec_out = (reinterpret_cast<uintptr_t>(u) % 16) == 0 ? 1 : 0;
-    launch(k_materialize_u, dim3(static_cast<unsigned>(za.nb)), dim3(kThreads), 0, s, za,
-                       sh, u, vec_out);
+    launch(k_materialize_u, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s, za, sh, u,
+           vec_out);
     return hipGetLastError();
 }
 
@@ -1366,7 +1738,8 @@ bool map_is_dense(int64_t M, int64_t N) { return N * kDenseRatio >= M; }
 
 bool finish_fits(const WArgs& wa, const ZArgs& za) {
     if (map_is_dense(wa.M, za.N)) return false;
-    return za.N > 0 && wa.nb >= 1 && wa.nb <= kBetaLds && za.nb >= 1 && za.nb <= kFinishMaxZBlocks;
+    return za.N > 0 && wa.nb >= 1 && wa.nb <= kBetaLds &&
+           (za.nb >= 1 || za.scheme != kSchemeMultinomial) && za.nb <= kFinishMaxZBlocks;
 }
 
 hipError_t launch_finish(int prec, const void* w, const WArgs& wa, const ZArgs& za,

@@ -143,6 +143,23 @@ def test_host_validation_batched(lib):
     assert call(ws_bytes=ws - 1) == 3
 
 
+def test_host_validation_schemes(lib):
+    ws = _ws(lib, 1000, 100)
+    f = lib.dcr_resample_scheme
+    # every call below fails on the host, before anything is enqueued
+    assert f(FAKE, 1000, 100, 1, 0, 0, 3, FAKE, None, None, None, FAKE, ws, None) == 2
+    assert f(FAKE, 1000, 100, 1, 0, 0, -1, FAKE, None, None, None, FAKE, ws, None) == 2
+    assert f(FAKE, 0, 100, 1, 0, 0, 1, FAKE, None, None, None, FAKE, ws, None) == 1
+    assert f(FAKE, 1000, 100, 1, 0, 0, 2, FAKE, None, None, None, FAKE, 16, None) == 3
+    assert f(FAKE, 1000, 100, 1, 0, 0, 1, None, None, None, None, FAKE, ws, None) == 1
+    g = lib.dcr_scheme_uniforms
+    assert g(10, 1, 0, 0, FAKE, None) == 2          # multinomial: use dcr_sorted_uniforms
+    assert g(10, 1, 0, 5, FAKE, None) == 2
+    assert g(-1, 1, 0, 1, FAKE, None) == 1
+    assert g(10, 1, 0, 1, None, None) == 1
+    assert g(0, 1, 0, 1, None, None) == 0           # N = 0: no-op
+
+
 def test_profile_api_host(lib):
     assert lib.dcr_profile_kind_count() >= 5
     names = [lib.dcr_profile_kind_name(k).decode() for k in range(lib.dcr_profile_kind_count())]
