@@ -84,9 +84,12 @@ def load_traffic(workload: str, precision: str, kernel: str):
     return e.get("bytes_per_launch")
 
 
-# rocprofv3 kernel-name fragment of each timed launch kind
+# kernel of each timed launch kind
 KERNEL_NAMES = {"reduce": "k_reduce", "finish": "k_finish", "map_dense": "k_map_dense",
-                "map_fused": "k_map_fused", "carries": "k_carries"}
+                "map_fused": "k_map_fused", "carries": "k_carries", "map_wide": "k_map_wide",
+                "batch_reduce": "k_reduce_batched", "batch_map": "k_map_batched",
+                "batch_carries": "k_carries_batched"}
+KIND_OF_KERNEL = {v: k for k, v in KERNEL_NAMES.items()}
 COPY_KERNEL = "neg_kernel"
 
 
@@ -97,42 +100,62 @@ def _counter_rows(path: str):
             yield row["Kernel_Name"], row["Counter_Name"], float(row["Counter_Value"])
 
 
-def _mean_per_dispatch(path: str, counter: str, name_part: str) -> float:
-    vals = [v for k, c, v in _counter_rows(path) if c == counter and name_part in k]
+def _per_kernel_means(path: str, counter: str) -> dict:
+    """Mean counter value per dispatch for each library kernel, keyed by
+    (bare kernel name, element type or None)."""
+    import re
+    acc = {}
+    for name, c, v in _counter_rows(path):
+        if c != counter:
+            continue
+        m = re.search(r"dcr::(k_\w+)(?:<(\w+))?", name)
+        if not m:
+            continue
+        acc.setdefault((m.group(1), m.group(2)), []).append(v)
+    return {k: sum(v) / len(v) for k, v in acc.items()}
+
+
+def _copy_mean(path: str, counter: str) -> float:
+    vals = [v for k, c, v in _counter_rows(path) if c == counter and COPY_KERNEL in k]
     if not vals:
-        raise SystemExit(f"{path}: no {counter} rows for a kernel named like {name_part}")
+        raise SystemExit(f"{path}: no {counter} rows for the copy kernel")
     return sum(vals) / len(vals)
 
 
 def write_traffic(args):
     """Turn four rocprofv3 --pmc CSV files (FETCH_SIZE and WRITE_SIZE of the
-    bench command and of the copy calibration) into bytes per launch, each
-    counter scaled by what it reads for the copy of known size."""
+    bench command, then of --calibrate-copy) into HBM bytes per launch of
+    every library kernel they cover, each counter scaled by what it reads for
+    the copy of known size."""
     fetch, write, cfetch, cwrite = args.write_traffic
     copy_kib = CALIBRATE_BYTES / 1024.0
-    f_scale = copy_kib / _mean_per_dispatch(cfetch, "FETCH_SIZE", COPY_KERNEL)
-    w_scale = copy_kib / _mean_per_dispatch(cwrite, "WRITE_SIZE", COPY_KERNEL)
-    kname = KERNEL_NAMES[args.traffic_kernel]
-    fk = _mean_per_dispatch(fetch, "FETCH_SIZE", kname) * f_scale
-    wk = _mean_per_dispatch(write, "WRITE_SIZE", kname) * w_scale
+    f_scale = copy_kib / _copy_mean(cfetch, "FETCH_SIZE")
+    w_scale = copy_kib / _copy_mean(cwrite, "WRITE_SIZE")
+    fk = _per_kernel_means(fetch, "FETCH_SIZE")
+    wk = _per_kernel_means(write, "WRITE_SIZE")
     try:
         with open(TRAFFIC_FILE) as f:
             d = json.load(f)
     except (OSError, ValueError):
         d = {}
-    d[f"{args.workload}/{args.precision}/{args.traffic_kernel}"] = {
-        "bytes_per_launch": (fk + wk) * 1024.0,
-        "fetch_kib_per_launch": fk,
-        "write_kib_per_launch": wk,
-        "copy_scale_fetch": f_scale,
-        "copy_scale_write": w_scale,
-        "source_digest": source_digest(kname),
-        "counter_files": [os.path.basename(x) for x in args.write_traffic],
-    }
+    for (bare, targ), fv in sorted(fk.items(), key=lambda kv: (kv[0][0], kv[0][1] or "")):
+        if bare not in KIND_OF_KERNEL or (bare, targ) not in wk:
+            continue
+        prec = {"float": "f32", "double": "f64"}.get(targ, args.precision)
+        workload = "batched" if bare.endswith("_batched") else args.workload
+        key = f"{workload}/{prec}/{KIND_OF_KERNEL[bare]}"
+        d[key] = {
+            "bytes_per_launch": (fv * f_scale + wk[(bare, targ)] * w_scale) * 1024.0,
+            "fetch_kib_per_launch": fv * f_scale,
+            "write_kib_per_launch": wk[(bare, targ)] * w_scale,
+            "copy_scale_fetch": f_scale,
+            "copy_scale_write": w_scale,
+            "source_digest": source_digest(bare),
+        }
+        print(key, json.dumps(d[key]))
     with open(TRAFFIC_FILE, "w") as f:
         json.dump(d, f, indent=1, sort_keys=True)
         f.write("\n")
-    print(json.dumps(d[f"{args.workload}/{args.precision}/{args.traffic_kernel}"]))
 
 
 CALIBRATE_BYTES = 1 << 30
@@ -206,6 +229,7 @@ def measure_batched(dcr, torch, dev, steps: int, warmup: int, cpu_seconds: float
     r0 = r.cpu().numpy()
     red_bytes = batched_reduce_bytes(bw.w_off, bw.n_off, 4)
     achieved = red_bytes / (kernels["batch_reduce"] * 1e-3) / 1e9
+    traffic = load_traffic("batched", "f32", "batch_reduce")
     out = {
         "workload": bw.description,
         "B": bw.B, "sum_M": int(w32.size), "sum_N": sumN,
@@ -217,7 +241,7 @@ def measure_batched(dcr, torch, dev, steps: int, warmup: int, cpu_seconds: float
         "kernels_ms": kernels,
         "roofline": {"kernel": "k_reduce_batched", "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "algorithmic_bytes": red_bytes,
+                     "traffic": traffic, "algorithmic_bytes": red_bytes,
                      "avg_launch_us": kernels["batch_reduce"] * 1e3},
     }
     if cpu_seconds > 0:
@@ -287,7 +311,6 @@ def main():
                     help="run only the copy of known size used to scale HBM counters")
     ap.add_argument("--write-traffic", nargs=4, metavar="CSV",
                     help="FETCH_SIZE, WRITE_SIZE csv of this command, then of --calibrate-copy")
-    ap.add_argument("--traffic-kernel", default="reduce", choices=sorted(KERNEL_NAMES))
     args = ap.parse_args()
     if args.write_traffic:
         write_traffic(args)
