@@ -326,7 +326,7 @@ constexpr int64_t kMaxSum = 1LL << 40;
 struct BatchLayout {
     int64_t wt_cap = 0, zt_cap = 0, mc_cap = 0;
     size_t head = 0, wt_base = 0, zt_base = 0, mc_base = 0, seg_status = 0, seg_totals = 0;
-    size_t wt_tot = 0, wt_beta = 0, wt_sub = 0, zt_tot = 0, zt_beta = 0, zrel = 0;
+    size_t wt_tot = 0, wt_beta = 0, wt_sub = 0, wt_chunk = 0, zt_tot = 0, zt_beta = 0, zrel = 0;
     size_t bytes = 0;
 };
 
@@ -350,6 +350,7 @@ BatchLayout make_batch_layout(int64_t B, int64_t sumM, int64_t sumN) {
     L.wt_tot = take(sizeof(double) * L.wt_cap);
     L.wt_beta = take(sizeof(double) * L.wt_cap);
     L.wt_sub = take(sizeof(double) * L.wt_cap * kWSubPerBlock);
+    L.wt_chunk = take(sizeof(double) * L.wt_cap * kWSubPerBlock * 16);
     L.zt_tot = take(sizeof(double) * L.zt_cap);
     L.zt_beta = take(sizeof(double) * L.zt_cap);
     L.zrel = take(sizeof(double) * (sumN + B));
@@ -402,6 +403,7 @@ dcr_status dcr_resample_batched(const void* w, const int64_t* w_off, const int64
     ba.wt_tot = at<double>(ws, L.wt_tot);
     ba.wt_beta = at<double>(ws, L.wt_beta);
     ba.wt_sub = at<double>(ws, L.wt_sub);
+    ba.wt_chunk = at<double>(ws, L.wt_chunk);
     ba.zt_tot = at<double>(ws, L.zt_tot);
     ba.zt_beta = at<double>(ws, L.zt_beta);
     ba.zrel = at<double>(ws, L.zrel);

@@ -193,6 +193,18 @@ __device__ __forceinline__ RawChunk<Tin> load_raw_any(const Tin* __restrict__ p)
     return r;
 }
 
+// A chunk of which only the first n values exist (n <= 0: none; nothing is
+// read beyond them), zero-padded; full chunks are vector-loaded.
+template <typename Tin>
+__device__ __forceinline__ RawChunk<Tin> load_raw_n(const Tin* __restrict__ p, int n) {
+    if (n >= kLane) return load_raw_any<Tin>(p);
+    RawChunk<Tin> rc;
+    constexpr int kPer = (sizeof(Tin) == 4) ? 4 : 2;
+#pragma unroll
+    for (int q = 0; q < kLane; ++q) rc.v[q / kPer][q % kPer] = (q < n) ? p[q] : static_cast<Tin>(0);
+    return rc;
+}
+
 // Left-to-right binary64 sum of a raw chunk; also folds its elements into a
 // running minimum (in the input precision) used to detect negative weights.
 template <typename Tin>

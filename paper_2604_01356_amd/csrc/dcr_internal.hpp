@@ -30,6 +30,7 @@ struct WArgs {
     double* blk_tot;   // [nb]   block totals (NaN: the block holds an inadmissible weight)
     double* beta;      // [nb]   block ends beta_1..beta_nb (monotone scan)
     double* sub_end;   // [nb*128] in-block sub-tile ends sigma_1..sigma_128
+    double* chunk_tot; // [nb*2048] lane-chunk totals, or null (kept only by the batched form)
 };
 
 // Sorted-uniform schemes: Alg. 1 (exponential spacings), stratified
@@ -112,6 +113,7 @@ struct BatchArgs {
     double* wt_tot;         // [wt_cap] weight-block totals
     double* wt_beta;        // [wt_cap] weight-block ends (per filter)
     double* wt_sub;         // [wt_cap * 128] sub-tile ends
+    double* wt_chunk;       // [wt_cap * 2048] lane-chunk totals
     double* zt_tot;         // [zt_cap]
     double* zt_beta;        // [zt_cap]
     double* zrel;           // [sumN + B] in-block spacing prefixes, filter b at n_off[b] + b

@@ -41,7 +41,6 @@ __device__ __forceinline__ int clamp_count(int64_t remaining, int cap) {
 // reach only ~85% of the coalesced bandwidth on this chip.
 // ---------------------------------------------------------------------------
 constexpr int kStreamDepth = 2;                     // rounds in flight beyond the current
-constexpr int kStreamBufs = kStreamDepth + 1;
 constexpr int kWaveRoundF32 = 64 * kLane;           // floats per wave per round (4 KB)
 constexpr int kWaves = kThreads / 64;
 
@@ -126,10 +125,12 @@ __device__ __forceinline__ void reduce_z_block(const ZArgs& za, int64_t g, doubl
 // sub-tile ends and the block total (NaN for an inadmissible block).  The
 // three LDS buffers stream binary32 weights; sb0 is also the epilogue's
 // scratch.  All threads call it.
-template <typename Tin>
+template <typename Tin, int DEPTH = kStreamDepth>
 __device__ __forceinline__ void reduce_w_block(const Tin* __restrict__ w, const WArgs& wa, int64_t b,
                                                int vec_ok, unsigned char* sb0, unsigned char* sb1,
                                                unsigned char* sb2) {
+    static_assert(DEPTH == 1 || DEPTH == 2, "one or two rounds in flight");
+    constexpr int kBufs = DEPTH + 1;
     double* lane_tot = reinterpret_cast<double*>(sb0);   // [kWIters][kThreads]
     double* sub_tot = lane_tot + kWIters * kThreads;      // [kWSubPerBlock]
     double* sub_end = sub_tot + kWSubPerBlock;            // [kWSubPerBlock]
@@ -145,15 +146,14 @@ __device__ __forceinline__ void reduce_w_block(const Tin* __restrict__ w, const 
     if constexpr (sizeof(Tin) == 4) {
         if (full && aligned) {
             done = true;
-            float* const bufs[kStreamBufs] = {reinterpret_cast<float*>(sb0),
-                                              reinterpret_cast<float*>(sb1),
-                                              reinterpret_cast<float*>(sb2)};
+            float* const bufs[3] = {reinterpret_cast<float*>(sb0), reinterpret_cast<float*>(sb1),
+                                    reinterpret_cast<float*>(sb2)};
             const int wv = t >> 6;
             const int l64 = t & 63;
             // the wave's rows 4wv..4wv+3 of round `it` are kWaveRoundF32 consecutive weights
             const float* src = reinterpret_cast<const float*>(w) + blk0 + wv * kWaveRoundF32;
             auto issue = [&](int it) {
-                float* dst = bufs[it % kStreamBufs] + wv * kWaveRoundF32;
+                float* dst = bufs[it % kBufs] + wv * kWaveRoundF32;
                 const float* g0 = src + it * (kWaves * kWaveRoundF32);
 #pragma unroll
                 for (int k = 0; k < kLane / 4; ++k)
@@ -161,18 +161,18 @@ __device__ __forceinline__ void reduce_w_block(const Tin* __restrict__ w, const 
             };
             float mn = 0.0f;
 #pragma unroll
-            for (int it = 0; it < kStreamDepth; ++it) issue(it);
+            for (int it = 0; it < DEPTH; ++it) issue(it);
 #pragma unroll
             for (int it = 0; it < kWIters; ++it) {
-                if (it + kStreamDepth < kWIters) {
-                    issue(it + kStreamDepth);
-                    wait_vm(kStreamDepth * (kLane / 4));
+                if (it + DEPTH < kWIters) {
+                    issue(it + DEPTH);
+                    wait_vm(DEPTH * (kLane / 4));
                 } else {
                     wait_vm((kWIters - 1 - it) * (kLane / 4));
                 }
                 __builtin_amdgcn_wave_barrier();
                 const f32x4* mine = reinterpret_cast<const f32x4*>(
-                    bufs[it % kStreamBufs] + wv * kWaveRoundF32 + l64 * kLane);
+                    bufs[it % kBufs] + wv * kWaveRoundF32 + l64 * kLane);
                 RawChunk<float> rc;
 #pragma unroll
                 for (int k = 0; k < kLane / 4; ++k) rc.v[k] = mine[k];
@@ -203,19 +203,30 @@ __device__ __forceinline__ void reduce_w_block(const Tin* __restrict__ w, const 
         bad = (mn < static_cast<Tin>(0)) ? 1 : 0;
     }
     if (!full) {
-#pragma unroll 1
+        // the array's ragged last block: the same lane-strided loop, each chunk
+        // zero-padded beyond the weights that exist (a NaN or infinity still
+        // reaches the block total, a negative weight the minimum)
+        const int64_t j00 = blk0 + row * kSub + lane * kLane;
+        const Tin* base = w + j00;
+        Tin mn = static_cast<Tin>(0);
+        RawChunk<Tin> cur = load_raw_n<Tin>(base, clamp_count(wa.M - j00, kLane));
+#pragma unroll
         for (int it = 0; it < kWIters; ++it) {
-            const int64_t j0 = blk0 + static_cast<int64_t>(it * kRows + row) * kSub + lane * kLane;
-            const int nv = clamp_count(wa.M - j0, kLane);
-            double x[kLane];
-            load_chunk<Tin>(w + (nv > 0 ? j0 : 0), nv, (vec_ok & 1) != 0, x);
-#pragma unroll
-            for (int k = 0; k < kLane; ++k) bad |= bad_weight(x[k]) ? 1 : 0;
-            const double ct = chunk_sum(x);
-#pragma unroll
-            for (int q = 0; q < kWIters; ++q)
-                if (q == it) lt[q] = ct;
+            RawChunk<Tin> nxt;
+            const int64_t jn = j00 + static_cast<int64_t>(it + 1) * kRows * kSub;
+            if (it + 1 < kWIters) nxt = load_raw_n<Tin>(base + (it + 1) * kRows * kSub,
+                                                       clamp_count(wa.M - jn, kLane));
+            lt[it] = raw_sum<Tin>(cur, mn);
+            if (it + 1 < kWIters) cur = nxt;
+            __builtin_amdgcn_sched_barrier(0);
         }
+        bad = (mn < static_cast<Tin>(0)) ? 1 : 0;
+    }
+    if (wa.chunk_tot) {
+        // lane chunk (sub-tile 16 it + row, lane) of the block: coalesced per round
+        double* ct = wa.chunk_tot + b * (kWSubPerBlock * kRowLanes);
+#pragma unroll
+        for (int it = 0; it < kWIters; ++it) ct[it * kThreads + t] = lt[it];
     }
     lds_barrier();   // the first stream buffer becomes the epilogue's scratch
 #pragma unroll
@@ -1223,6 +1234,7 @@ __device__ __forceinline__ WArgs seg_wargs(const BatchArgs& ba, int b) {
     a.blk_tot = ba.wt_tot + t0;
     a.beta = ba.wt_beta + t0;
     a.sub_end = ba.wt_sub + t0 * kWSubPerBlock;
+    a.chunk_tot = ba.wt_chunk + t0 * (kWSubPerBlock * kRowLanes);
     return a;
 }
 
@@ -1345,17 +1357,6 @@ __device__ __forceinline__ int64_t seg_block_of(const WArgs& wa, const double* s
             bhi = mid;
     }
     return blo;
-}
-
-// The same kept unconverted in registers (binary32 stays 4 bytes a value).
-template <typename Tin>
-__device__ __forceinline__ RawChunk<Tin> seg_load_raw(const Tin* __restrict__ p, int n) {
-    if (n == kLane) return load_raw_any<Tin>(p);
-    RawChunk<Tin> rc;
-    constexpr int kPer = (sizeof(Tin) == 4) ? 4 : 2;
-#pragma unroll
-    for (int q = 0; q < kLane; ++q) rc.v[q / kPer][q % kPer] = (q < n) ? p[q] : static_cast<Tin>(0);
-    return rc;
 }
 
 template <typename Tin>
@@ -1506,7 +1507,14 @@ __device__ void map_seg_chunk(const Tin* __restrict__ w, const WArgs& wa, const 
     const int lane = t % kRowLanes;
     for (int p0 = 0; p0 < ntouched; p0 += kSegPass) {
         const int p1 = (p0 + kSegPass < ntouched) ? p0 + kSegPass : ntouched;
-        // chunk totals: thread (row, lane) sums chunk `lane` of sub-tiles p0+row+16m
+        // chunk totals: thread (row, lane) takes chunk `lane` of sub-tiles
+        // p0+row+16m, stored by the reduce when it kept them, else re-summed
+        if (wa.chunk_tot) {
+#pragma unroll 4
+            for (int k = p0 + row; k < p1; k += kRows)
+                L.crun[(k - p0) * kRowLanes + lane] =
+                    wa.chunk_tot[static_cast<int64_t>(L.lsub[k]) * kRowLanes + lane];
+        } else {
 #pragma unroll 4
         for (int k = p0 + row; k < p1; k += kRows) {
             const int32_t g = L.lsub[k];
@@ -1516,12 +1524,13 @@ __device__ void map_seg_chunk(const Tin* __restrict__ w, const WArgs& wa, const 
             const int nv = clamp_count(wa.M - j0, kLane);
             const int64_t bend = b * kWBlock + kWBlock;
             const int nvb = (j0 + nv <= bend) ? nv : static_cast<int>(bend - j0);
-            const RawChunk<Tin> rc = seg_load_raw<Tin>(w + (nvb > 0 ? j0 : 0), nvb > 0 ? nvb : 0);
+            const RawChunk<Tin> rc = load_raw_n<Tin>(w + (nvb > 0 ? j0 : 0), nvb > 0 ? nvb : 0);
             // left to right from the first value, as k_reduce sums a chunk
             double cs = rc.at(0);
 #pragma unroll
             for (int q = 1; q < kLane; ++q) cs = cs + rc.at(q);
             L.crun[(k - p0) * kRowLanes + lane] = cs;
+        }
         }
         lds_barrier();
         // running sums c_{l+1} = c_l + t_l, left to right
@@ -1584,7 +1593,7 @@ __device__ void map_seg_chunk(const Tin* __restrict__ w, const WArgs& wa, const 
                             ? ((slen - lc[m] * kLane < kLane) ? slen - lc[m] * kLane : kLane)
                             : 0;
                 j0[m] += lc[m] * kLane;
-                xv[m] = seg_load_raw<Tin>(w + (nv[m] > 0 ? j0[m] : 0), nv[m]);
+                xv[m] = load_raw_n<Tin>(w + (nv[m] > 0 ? j0[m] : 0), nv[m]);
             }
 #pragma unroll
             for (int m = 0; m < kSegDraws; ++m) {
