@@ -108,7 +108,7 @@ struct BatchArgs {
     int64_t sumM_cap, sumN_cap;
     int64_t* wt_base;       // [B+1] first weight block of each filter (k_batch_plan)
     int64_t* zt_base;       // [B+1] first spacing block
-    int64_t* mc_base;       // [B+1] first map chunk (1024 draws)
+    int64_t* mc_base;       // [B+1] first map chunk (512 draws)
     int32_t* head;          // [0] plan status, [1] batch status
     double* wt_tot;         // [wt_cap] weight-block totals
     double* wt_beta;        // [wt_cap] weight-block ends (per filter)
@@ -123,7 +123,7 @@ struct BatchArgs {
 constexpr int kPlanThreads = 1024;
 constexpr int64_t kBatchWBlock = 32768;
 constexpr int64_t kBatchZBlock = 4096;
-constexpr int64_t kBatchChunk = 1024;
+constexpr int64_t kBatchChunk = 512;
 // The batched launches, in order: plan, reduce, carries, map.
 hipError_t launch_batch_plan(const BatchArgs& ba, int32_t* dev_status, hipStream_t s);
 hipError_t launch_reduce_batched(int prec, const void* w, const BatchArgs& ba, hipStream_t s);

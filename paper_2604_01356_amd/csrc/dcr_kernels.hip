@@ -1315,12 +1315,12 @@ __global__ __launch_bounds__(kScanThreads) void k_carries_batched(BatchArgs ba) 
 // Comparisons are of unnormalised partial sums S_j with the threshold x of
 // each draw (S_j >= x  <=>  W_j >= u).  Sums follow k_reduce's order.
 // ---------------------------------------------------------------------------
-constexpr int kSegU = 1024;                  // draws per workgroup
+constexpr int kSegU = 512;                   // draws per workgroup
 constexpr int kSegPer = kSegU / kThreads;
-constexpr int kSegBetaLds = 512;             // block ends kept in LDS (sampled beyond)
-constexpr int kSegSubBlocks = 8;             // blocks whose sub-tile ends are staged
-constexpr int kSegPass = 128;                // touched sub-tiles per chunk pass
-constexpr int kSegDraws = 3;                 // draws per thread in flight at the element level
+constexpr int kSegBetaLds = 128;             // block ends kept in LDS (sampled beyond)
+constexpr int kSegSubBlocks = 4;             // blocks whose sub-tile ends are staged
+constexpr int kSegPass = 64;                 // touched sub-tiles per chunk pass
+constexpr int kSegDraws = 1;                 // draws per thread in flight at the element level
 static_assert(kBatchChunk == kSegU, "a map chunk is the draws of one k_map_batched workgroup");
 
 struct SegLds {
