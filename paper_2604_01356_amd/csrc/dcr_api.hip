@@ -24,7 +24,7 @@ constexpr int64_t kMaxN = 2147483646LL;   // N + 1 draws must stay below 2^31
 constexpr int64_t kWBlock = 32768;
 constexpr int64_t kWSubPerBlock = 128;
 constexpr int64_t kZBlock = 4096;
-constexpr int64_t kDenseU = 4096;   // uniforms per workgroup of the dense map
+constexpr int64_t kDenseMinPerWG = 256;   // fewest uniforms per workgroup of the dense map
 
 size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
@@ -66,7 +66,7 @@ Layout make_layout(int64_t M, int64_t N, int scheme = dcr::kSchemeMultinomial) {
     }
     if (N > 0) {
         L.wide = off;
-        off = align256(off + sizeof(int32_t) * ((N + kDenseU - 1) / kDenseU));
+        off = align256(off + sizeof(int32_t) * ((N + kDenseMinPerWG - 1) / kDenseMinPerWG));
     }
     L.bytes = off;
     return L;

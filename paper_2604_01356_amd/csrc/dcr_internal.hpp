@@ -68,9 +68,9 @@ bool finish_fits(const WArgs& wa, const ZArgs& za);
 // the windowed linear merge (k_map_dense) instead of one search per uniform.
 constexpr int64_t kDenseRatio = 4;
 bool map_is_dense(int64_t M, int64_t N);
-int64_t dense_chunks(int64_t N);
+int64_t dense_chunks(int64_t M, int64_t N);   // at most ceil(N / 256)
 // k_map_dense: merges each chunk of 4096 draws and flags in `wide`
-// (dense_chunks(N) int32 flags) the chunks whose span is too wide to merge;
+// (dense_chunks(M, N) int32 flags) the chunks whose span is too wide to merge;
 // launch_map_wide then places the draws of the flagged chunks.
 hipError_t launch_map_dense(int prec, const void* w, const WArgs& wa, const ZArgs& za,
                             const SharedArgs& sh, double* u_out, int32_t* r, int32_t* wide,

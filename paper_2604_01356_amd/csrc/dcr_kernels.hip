@@ -206,19 +206,21 @@ __device__ __forceinline__ void reduce_w_block(const Tin* __restrict__ w, const 
         // the array's ragged last block: the same lane-strided loop, each chunk
         // zero-padded beyond the weights that exist (a NaN or infinity still
         // reaches the block total, a negative weight the minimum)
+        // (kept rolled: only one block of an array takes this path)
         const int64_t j00 = blk0 + row * kSub + lane * kLane;
         const Tin* base = w + j00;
         Tin mn = static_cast<Tin>(0);
         RawChunk<Tin> cur = load_raw_n<Tin>(base, clamp_count(wa.M - j00, kLane));
-#pragma unroll
+#pragma unroll 1
         for (int it = 0; it < kWIters; ++it) {
-            RawChunk<Tin> nxt;
             const int64_t jn = j00 + static_cast<int64_t>(it + 1) * kRows * kSub;
-            if (it + 1 < kWIters) nxt = load_raw_n<Tin>(base + (it + 1) * kRows * kSub,
-                                                       clamp_count(wa.M - jn, kLane));
-            lt[it] = raw_sum<Tin>(cur, mn);
-            if (it + 1 < kWIters) cur = nxt;
-            __builtin_amdgcn_sched_barrier(0);
+            const int nn = (it + 1 < kWIters) ? clamp_count(wa.M - jn, kLane) : 0;
+            const RawChunk<Tin> nxt = load_raw_n<Tin>(base + (nn > 0 ? (it + 1) * kRows * kSub : 0), nn);
+            const double ct = raw_sum<Tin>(cur, mn);
+#pragma unroll
+            for (int q = 0; q < kWIters; ++q)
+                if (q == it) lt[q] = ct;
+            cur = nxt;
         }
         bad = (mn < static_cast<Tin>(0)) ? 1 : 0;
     }
@@ -693,6 +695,45 @@ __device__ SubtileLoc locate_subtile(const WArgs& wa, const double* sbeta, int64
     return L;
 }
 
+// The global sub-tile index alone (block * 128 + sub-tile) of the same
+// search, reading the block's sub-tile ends eight at a time (few registers).
+__device__ int64_t locate_subtile_index(const WArgs& wa, const double* sbeta, int64_t kstride,
+                                        int ns, double x, int qi) {
+    const int64_t nb = wa.nb;
+    int qlo = 0, qhi = ns - 1;
+    while (qlo < qhi) {
+        const int mid = (qlo + qhi) >> 1;
+        if (sbeta[mid] < x)
+            qlo = mid + 1;
+        else
+            qhi = mid;
+    }
+    int64_t lo = static_cast<int64_t>(qlo) * kstride;
+    int64_t hi = ((static_cast<int64_t>(qlo) + 1) * kstride < nb ? (qlo + 1) * kstride : nb) - 1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (wa.beta[mid] < x)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    const int64_t b = lo;
+    const double beta_b = (b == 0) ? 0.0 : wa.beta[b - 1];
+    const double beta_n = wa.beta[b];
+    const int64_t blen = (wa.M - b * kWBlock < kWBlock) ? wa.M - b * kWBlock : kWBlock;
+    const int nsub = static_cast<int>((blen + kSub - 1) / kSub);
+    const double* se = wa.sub_end + b * kWSubPerBlock;
+    constexpr int kPerLane = kWSubPerBlock / kQuad;
+    int cnt = 0;
+    for (int c8 = 0; c8 < kPerLane; c8 += 8) {
+        const int s0 = kPerLane * qi + c8;
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            cnt += (s0 + k < nsub - 1 && fmin(beta_b + se[s0 + k], beta_n) < x) ? 1 : 0;
+    }
+    return b * kWSubPerBlock + quad_sum(cnt);
+}
+
 template <typename Tin>
 __device__ void map_quad(const Tin* __restrict__ w, const WArgs& wa, const double* sbeta,
                          int64_t kstride, int ns, double x, int64_t i, int qi,
@@ -832,34 +873,38 @@ __global__ __launch_bounds__(kThreads) void k_map_fused(const Tin* __restrict__ 
 // ---------------------------------------------------------------------------
 // Inverse CMF in the dense regime (several uniforms per sub-tile: the
 // linear-merge limit of Alg. 5, where it behaves like Alg. 4).  A workgroup
-// takes 4096 consecutive uniforms; the first and the last are located by the
-// quad search, which bounds the sub-tiles all of them fall in (the split of
-// Alg. 5).  That span is re-summed, 16 sub-tiles (4096 weights) at a time,
-// and the merge of Alg. 4 is split by weights: each thread holds 16
-// consecutive normalised cumulative weights in registers (the values of
-// k_materialize_w), finds the run of the workgroup's sorted uniforms that falls
-// in its 16 bins by two searches of the uniforms in LDS, and places each of
-// them with 16 register comparisons.  A span wider than 64 sub-tiles is
-// flagged and left to k_map_wide (one quad search per uniform).
+// takes `per_wg` consecutive uniforms (16 per thread), chosen so that their
+// span of weights usually fits one window of 16 sub-tiles; the first and the
+// last are located by the quad search, which bounds the sub-tiles all of
+// them fall in (the split of Alg. 5).  The span is re-summed a window at a
+// time into LDS as normalised cumulative weights (the values of
+// k_materialize_w); then every thread places its own 16 sorted uniforms that
+// end in the window: a search for the first, galloping forward for the
+// others (the merge of Alg. 4, one run of uniforms per thread, so the work is
+// the same for every thread however the weights are spread).  A span wider
+// than 64 sub-tiles is flagged and left to k_map_wide (one quad search per
+// uniform).
 // ---------------------------------------------------------------------------
-constexpr int kDenseU = 4096;
-constexpr int kDensePer = kDenseU / kThreads;
+constexpr int kDenseU = 4096;                 // most uniforms per workgroup
+constexpr int kDensePer = kDenseU / kThreads;  // per thread
 constexpr int kWinSub = 16;
+constexpr int kWinLen = kWinSub * kSub;       // weights per window (= kThreads * kLane)
 constexpr int kMaxWin = 4;
+static_assert(kWinLen <= kBetaLds, "the window reuses the block-end stage");
 
 template <typename Tin>
-__global__ __launch_bounds__(kThreads) void k_map_dense(const Tin* __restrict__ w, WArgs wa, ZArgs za,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_map_dense(const Tin* __restrict__ w, WArgs wa, ZArgs za,
                                                         SharedArgs sh, double* __restrict__ u_out,
                                                         int32_t* __restrict__ r,
-                                                        int32_t* __restrict__ wide, int vec_ok) {
-    // block ends for the search of the span, then this workgroup's uniforms
-    __shared__ double lds[kBetaLds > kDenseU ? kBetaLds : kDenseU];
+                                                        int32_t* __restrict__ wide, int vec_ok,
+                                                        int per_wg) {
+    // block ends for the search of the span, then a window of normalised
+    // cumulative weights
+    __shared__ double lds[kBetaLds];
     double* const sbeta = lds;
-    double* const su = lds;
+    double* const sw = lds;
     __shared__ double uends[2];
     __shared__ double ltot[kThreads];
-    __shared__ double wlast[kThreads];   // last normalised weight of each thread's 16
-    __shared__ int32_t rloc[kDenseU];    // the chunk's indices, stored coalesced at the end
     __shared__ int64_t span_ends[2];
     const int t = threadIdx.x;
     const int64_t N = za.N;
@@ -870,45 +915,42 @@ __global__ __launch_bounds__(kThreads) void k_map_dense(const Tin* __restrict__ 
         const int64_t b = (static_cast<int64_t>(q) + 1) * kstride - 1;
         sbeta[q] = wa.beta[b < nb ? b : nb - 1];
     }
-    const int64_t c0 = static_cast<int64_t>(blockIdx.x) * kDenseU;
-    const int64_t c1 = (c0 + kDenseU < N) ? c0 + kDenseU : N;
+    const int64_t c0 = static_cast<int64_t>(blockIdx.x) * per_wg;
+    const int64_t c1 = (c0 + per_wg < N) ? c0 + per_wg : N;
     const int nu = static_cast<int>(c1 - c0);
     const bool ok = sh.status[0] == kStatusOk;
     const double total = sh.totals[0];
     const double ztot = sh.totals[1];
     const int64_t iu0 = c0 + static_cast<int64_t>(t) * kDensePer;
     const int nmine = clamp_count(c1 - iu0, kDensePer);
-    // this thread's 16 draws lie in one spacing block (16 divides 4096): load
-    // their in-block prefixes at once, then form the uniforms
+    // this thread's 16 draws lie in one spacing block (16 divides 4096 and
+    // per_wg): load their in-block prefixes at once, then form the uniforms
     double us[kDensePer];
-    if (za.scheme != kSchemeMultinomial) {
-#pragma unroll
-        for (int q = 0; q < kDensePer; ++q) us[q] = 0.0;
-    } else if (nmine == kDensePer) {
-        const f64x2* q2 = reinterpret_cast<const f64x2*>(za.zrel + iu0);
-#pragma unroll
-        for (int v = 0; v < kDensePer / 2; ++v) {
-            const f64x2 d = q2[v];
-            us[2 * v] = d.x;
-            us[2 * v + 1] = d.y;
-        }
-    } else {
-#pragma unroll
-        for (int q = 0; q < kDensePer; ++q) us[q] = (q < nmine) ? za.zrel[iu0 + q] : 0.0;
-    }
-    const int64_t gz = iu0 / kZBlock;
     const bool spacings = za.scheme == kSchemeMultinomial;
-    const double zb = (!spacings || gz == 0) ? 0.0 : za.beta[gz - 1];
-    const double zn = spacings ? za.beta[gz < za.nb ? gz : za.nb - 1] : 0.0;
-    if (za.scheme != kSchemeMultinomial) {
+    if (!spacings) {
 #pragma unroll
         for (int q = 0; q < kDensePer; ++q) us[q] = (q < nmine) ? scheme_uniform(za, iu0 + q) : 0.0;
     } else {
+        if (nmine == kDensePer) {
+            const f64x2* q2 = reinterpret_cast<const f64x2*>(za.zrel + iu0);
+#pragma unroll
+            for (int v = 0; v < kDensePer / 2; ++v) {
+                const f64x2 d = q2[v];
+                us[2 * v] = d.x;
+                us[2 * v + 1] = d.y;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < kDensePer; ++q) us[q] = (q < nmine) ? za.zrel[iu0 + q] : 0.0;
+        }
+        const int64_t gz = iu0 / kZBlock;
+        const double zb = (gz == 0) ? 0.0 : za.beta[gz - 1];
+        const double zn = za.beta[gz < za.nb ? gz : za.nb - 1];
 #pragma unroll
         for (int q = 0; q < kDensePer; ++q) us[q] = uniform_of(us[q], iu0 + q, N, zb, zn, ztot);
     }
     if (u_out) store_uniforms(u_out, iu0, nmine, us, (reinterpret_cast<uintptr_t>(u_out) & 15) == 0);
-    if (nmine > 0 && t * kDensePer == 0) uends[0] = us[0];
+    if (nmine > 0 && t == 0) uends[0] = us[0];
 #pragma unroll
     for (int q = 0; q < kDensePer; ++q)
         if (t * kDensePer + q == nu - 1) uends[1] = us[q];
@@ -921,99 +963,100 @@ __global__ __launch_bounds__(kThreads) void k_map_dense(const Tin* __restrict__ 
     // global sub-tile ids of the first and the last uniform (quads 0 and 1)
     if (t < 2 * kQuad) {
         const double xe = threshold_for(uends[(t < kQuad) ? 0 : 1], total);
-        const SubtileLoc loc = locate_subtile(wa, sbeta, kstride, ns, xe, t & (kQuad - 1));
-        if ((t & (kQuad - 1)) == 0) span_ends[t / kQuad] = loc.b * kWSubPerBlock + loc.s;
+        const int64_t g = locate_subtile_index(wa, sbeta, kstride, ns, xe, t & (kQuad - 1));
+        if ((t & (kQuad - 1)) == 0) span_ends[t / kQuad] = g;
     }
     lds_barrier();
     const int64_t gs0 = span_ends[0], gs1 = span_ends[1];
     const bool is_wide = gs1 - gs0 + 1 > static_cast<int64_t>(kWinSub) * kMaxWin;
     if (t == 0) wide[blockIdx.x] = is_wide ? 1 : 0;
     if (is_wide) return;
-    // the block ends are no longer needed: the uniforms take their place
-#pragma unroll
-    for (int q = 0; q < kDensePer; ++q) su[t * kDensePer + q] = us[q];
     const int row = t / kRowLanes;
     const int lane = t % kRowLanes;
-    double wprev_window = -__builtin_huge_val();   // last weight before the current window
+    int32_t res[kDensePer];
+    int next = 0;   // this thread's first draw not placed yet (the draws are sorted)
+#pragma unroll
+    for (int q = 0; q < kDensePer; ++q) res[q] = 0;
     for (int64_t ws0 = gs0; ws0 <= gs1; ws0 += kWinSub) {
         const int nw = static_cast<int>((gs1 - ws0 + 1 < kWinSub) ? gs1 - ws0 + 1 : kWinSub);
         // re-sum the window: row r takes global sub-tile ws0 + r, so thread t
-        // holds the normalised cumulative weights of window entries 16t..16t+15
+        // writes window entries 16t .. 16t+15
         const int64_t gs = ws0 + row;
         const int64_t b = gs / kWSubPerBlock;
         const int sb = static_cast<int>(gs % kWSubPerBlock);
         const int64_t blk0 = b * kWBlock;
         const int64_t j0 = blk0 + static_cast<int64_t>(sb) * kSub + lane * kLane;
         const int nv = (row < nw) ? clamp_count(wa.M - j0, kLane) : 0;
-        double xv[kLane];
-        load_chunk<Tin>(w + (nv > 0 ? j0 : 0), nv, (vec_ok & 1) != 0, xv);
-        double p[kLane];
-        p[0] = xv[0];
-#pragma unroll
-        for (int k = 1; k < kLane; ++k) p[k] = p[k - 1] + xv[k];
-        ltot[t] = p[kLane - 1];
-        lds_barrier();
-        double lv[kRowLanes];
-#pragma unroll
-        for (int k = 0; k < kRowLanes; ++k) lv[k] = ltot[row * kRowLanes + k];
-        double c = 0.0;
-#pragma unroll
-        for (int k = 0; k < kRowLanes; ++k)
-            if (k < lane) c = c + lv[k];
-        // normalised cumulative weights (the values of k_materialize_w);
-        // entries past the end of the weights read +inf
-        double wv[kLane];
+        // every load of the window first: its weights and the bases they need
+        double sigma = 0.0, beta_b = 0.0, beta_n = 0.0;
         if (nv > 0) {
-            const double sigma = (sb == 0) ? 0.0 : wa.sub_end[b * kWSubPerBlock + sb - 1];
-            const double beta_b = (b == 0) ? 0.0 : wa.beta[b - 1];
-            const double beta_n = wa.beta[b];
-            const int64_t jlast = ((blk0 + kWBlock < wa.M) ? blk0 + kWBlock : wa.M) - 1;
-#pragma unroll
-            for (int k = 0; k < kLane; ++k) {
-                const double S =
-                    (j0 + k == jlast) ? beta_n : fmin(beta_b + (sigma + (c + p[k])), beta_n);
-                wv[k] = (k < nv) ? S / total : __builtin_huge_val();
-            }
-        } else {
-#pragma unroll
-            for (int k = 0; k < kLane; ++k) wv[k] = __builtin_huge_val();
+            sigma = (sb == 0) ? 0.0 : wa.sub_end[b * kWSubPerBlock + sb - 1];
+            beta_b = (b == 0) ? 0.0 : wa.beta[b - 1];
+            beta_n = wa.beta[b];
         }
-        wlast[t] = wv[kLane - 1];
+        const RawChunk<Tin> rc = load_raw_n<Tin>(w + (nv > 0 ? j0 : 0), nv);
+        {
+            double pt = rc.at(0);
+#pragma unroll
+            for (int k = 1; k < kLane; ++k) pt = pt + rc.at(k);
+            ltot[t] = pt;
+        }
         lds_barrier();
-        // this thread's bins take the uniforms u with  lower < u <= upper;
-        // threads past the window's last sub-tile take none
-        const double lower = (t == 0) ? wprev_window : wlast[t - 1];
-        const double upper = wv[kLane - 1];
-        // first uniform > lower and first uniform > upper (searches over su)
-        int a = 0, e = 0;
-        if (row < nw) {
+        double c = 0.0;
+        for (int k = 0; k < lane; ++k) c = c + ltot[row * kRowLanes + k];
+        // normalised cumulative weights (the in-chunk prefixes summed again
+        // from the raw values, same order); entries past the weights read +inf
+        const int64_t jlast = ((blk0 + kWBlock < wa.M) ? blk0 + kWBlock : wa.M) - 1;
+        double pk = 0.0;
 #pragma unroll
-            for (int step = kDenseU; step >= 1; step >>= 1) {
-                if (a + step <= nu && su[a + step - 1] <= lower) a += step;
-                if (e + step <= nu && su[e + step - 1] <= upper) e += step;
+        for (int k = 0; k < kLane; ++k) {
+            pk = (k == 0) ? rc.at(0) : pk + rc.at(k);
+            const double S = (j0 + k == jlast) ? beta_n : fmin(beta_b + (sigma + (c + pk)), beta_n);
+            sw[t * kLane + k] = (k < nv) ? S / total : __builtin_huge_val();
+        }
+        lds_barrier();
+        // entries of the window that exist, and the last one's value
+        const int64_t wlen64 = wa.M - ws0 * kSub;
+        const int nwin = (nw * kSub < wlen64) ? nw * kSub : static_cast<int>(wlen64);
+        const double wend = sw[nwin - 1];
+        // place this thread's draws that end in the window: u <= wend
+        int pos = 0;
+#pragma unroll
+        for (int q = 0; q < kDensePer; ++q) {
+            if (q >= next && q < nmine && us[q] <= wend) {
+                const double x = us[q];
+                // first j >= pos with sw[j] >= x: gallop, then bisect
+                if (sw[pos] < x) {
+                    int lo = pos, step = 1;   // sw[lo] < x
+                    while (lo + step < nwin - 1 && sw[lo + step] < x) {
+                        lo += step;
+                        step <<= 1;
+                    }
+                    int hi = (lo + step < nwin - 1) ? lo + step : nwin - 1;   // sw[hi] >= x
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (sw[mid] < x)
+                            lo = mid;
+                        else
+                            hi = mid;
+                    }
+                    pos = hi;
+                }
+                res[q] = static_cast<int32_t>(ws0 * kSub + pos);
+                next = q + 1;
             }
         }
-        const int64_t jbase = ws0 * kSub + static_cast<int64_t>(t) * kLane;
-        for (int iu = a; iu < e; ++iu) {
-            const double x = su[iu];
-            int cnt = 0;
-#pragma unroll
-            for (int k = 0; k < kLane; ++k) cnt += (wv[k] < x) ? 1 : 0;
-            rloc[iu] = static_cast<int32_t>(jbase + cnt);
-        }
-        wprev_window = wlast[nw * kRowLanes - 1];
-        lds_barrier();   // ltot / wlast are rewritten by the next window
+        lds_barrier();   // ltot and the window are rewritten by the next window
     }
-    // every draw of the chunk has been placed in exactly one thread's bins
-    const int i0 = t * kDensePer;
     if (nmine == kDensePer && (reinterpret_cast<uintptr_t>(r + iu0) & 15) == 0) {
         int4* dst = reinterpret_cast<int4*>(r + iu0);
 #pragma unroll
         for (int v = 0; v < kDensePer / 4; ++v)
-            dst[v] = make_int4(rloc[i0 + 4 * v], rloc[i0 + 4 * v + 1], rloc[i0 + 4 * v + 2],
-                               rloc[i0 + 4 * v + 3]);
+            dst[v] = make_int4(res[4 * v], res[4 * v + 1], res[4 * v + 2], res[4 * v + 3]);
     } else {
-        for (int q = 0; q < nmine; ++q) r[iu0 + q] = rloc[i0 + q];
+#pragma unroll
+        for (int q = 0; q < kDensePer; ++q)
+            if (q < nmine) r[iu0 + q] = res[q];
     }
 }
 
@@ -1022,7 +1065,7 @@ template <typename Tin>
 __global__ __launch_bounds__(kThreads) void k_map_wide(const Tin* __restrict__ w, WArgs wa, ZArgs za,
                                                        SharedArgs sh, int32_t* __restrict__ r,
                                                        const int32_t* __restrict__ wide,
-                                                       int vec_ok) {
+                                                       int vec_ok, int per_wg) {
     __shared__ double sbeta[kBetaLds];
     if (wide[blockIdx.x] == 0) return;   // workgroup-uniform
     const int t = threadIdx.x;
@@ -1036,8 +1079,8 @@ __global__ __launch_bounds__(kThreads) void k_map_wide(const Tin* __restrict__ w
     lds_barrier();
     const double total = sh.totals[0];
     const double ztot = sh.totals[1];
-    const int64_t c0 = static_cast<int64_t>(blockIdx.x) * kDenseU;
-    const int64_t c1 = (c0 + kDenseU < za.N) ? c0 + kDenseU : za.N;
+    const int64_t c0 = static_cast<int64_t>(blockIdx.x) * per_wg;
+    const int64_t c1 = (c0 + per_wg < za.N) ? c0 + per_wg : za.N;
     for (int64_t i = c0 + t / kQuad; i < c1; i += kUPerWG) {
         const double x = threshold_for(uniform_at(za, ztot, i), total);
         map_quad<Tin>(w, wa, sbeta, kstride, ns, x, i, t & (kQuad - 1), r, vec_ok);
@@ -1713,19 +1756,34 @@ hipError_t launch_map_fused(int prec, const void* w, const WArgs& wa, const ZArg
     return hipGetLastError();
 }
 
-int64_t dense_chunks(int64_t N) { return (N + kDenseU - 1) / kDenseU; }
+// Uniforms per dense-map workgroup: about 13/16 of a window's weights' worth
+// (per_wg * M / N), a multiple of 256 in [256, 4096].
+int dense_per_wg(int64_t M, int64_t N) {
+    const double want = static_cast<double>(kWinLen) * 13.0 / 16.0 * static_cast<double>(N) /
+                        static_cast<double>(M);
+    int64_t q = static_cast<int64_t>(want) / kThreads * kThreads;
+    if (q < kThreads) q = kThreads;
+    if (q > kDenseU) q = kDenseU;
+    return static_cast<int>(q);
+}
+
+int64_t dense_chunks(int64_t M, int64_t N) {
+    const int per = dense_per_wg(M, N);
+    return (N + per - 1) / per;
+}
 
 hipError_t launch_map_dense(int prec, const void* w, const WArgs& wa, const ZArgs& za,
                             const SharedArgs& sh, double* u_out, int32_t* r, int32_t* wide,
                             int vec_ok, hipStream_t s) {
     if (za.N <= 0) return hipSuccess;
-    const int64_t grid = dense_chunks(za.N);
+    const int per = dense_per_wg(wa.M, za.N);
+    const int64_t grid = dense_chunks(wa.M, za.N);
     if (prec == kPrecFP32)
-        launch(k_map_dense<float>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0,
-                           s, static_cast<const float*>(w), wa, za, sh, u_out, r, wide, vec_ok);
+        launch(k_map_dense<float>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s,
+               static_cast<const float*>(w), wa, za, sh, u_out, r, wide, vec_ok, per);
     else
-        launch(k_map_dense<double>, dim3(static_cast<unsigned>(grid)), dim3(kThreads),
-                           0, s, static_cast<const double*>(w), wa, za, sh, u_out, r, wide, vec_ok);
+        launch(k_map_dense<double>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s,
+               static_cast<const double*>(w), wa, za, sh, u_out, r, wide, vec_ok, per);
     return hipGetLastError();
 }
 
@@ -1733,13 +1791,14 @@ hipError_t launch_map_wide(int prec, const void* w, const WArgs& wa, const ZArgs
                            const SharedArgs& sh, int32_t* r, const int32_t* wide, int vec_ok,
                            hipStream_t s) {
     if (za.N <= 0) return hipSuccess;
-    const int64_t grid = dense_chunks(za.N);
+    const int per = dense_per_wg(wa.M, za.N);
+    const int64_t grid = dense_chunks(wa.M, za.N);
     if (prec == kPrecFP32)
-        launch(k_map_wide<float>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0,
-                           s, static_cast<const float*>(w), wa, za, sh, r, wide, vec_ok);
+        launch(k_map_wide<float>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s,
+               static_cast<const float*>(w), wa, za, sh, r, wide, vec_ok, per);
     else
-        launch(k_map_wide<double>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0,
-                           s, static_cast<const double*>(w), wa, za, sh, r, wide, vec_ok);
+        launch(k_map_wide<double>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s,
+               static_cast<const double*>(w), wa, za, sh, r, wide, vec_ok, per);
     return hipGetLastError();
 }
 
