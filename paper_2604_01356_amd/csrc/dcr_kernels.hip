@@ -903,7 +903,6 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     __shared__ double lds[kBetaLds];
     double* const sbeta = lds;
     double* const sw = lds;
-    __shared__ double uends[2];
     __shared__ double ltot[kThreads];
     __shared__ int64_t span_ends[2];
     const int t = threadIdx.x;
@@ -923,6 +922,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     const double ztot = sh.totals[1];
     const int64_t iu0 = c0 + static_cast<int64_t>(t) * kDensePer;
     const int nmine = clamp_count(c1 - iu0, kDensePer);
+    // the first and the last uniform of the chunk, for the span search by
+    // quads 0 and 1: formed first, so that the search overlaps the rest
+    double uend = 0.0;
+    if (t < 2 * kQuad && nu > 0) uend = uniform_at(za, ztot, (t < kQuad) ? c0 : c1 - 1);
     // this thread's 16 draws lie in one spacing block (16 divides 4096 and
     // per_wg): load their in-block prefixes at once, then form the uniforms
     double us[kDensePer];
@@ -949,12 +952,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
 #pragma unroll
         for (int q = 0; q < kDensePer; ++q) us[q] = uniform_of(us[q], iu0 + q, N, zb, zn, ztot);
     }
-    if (u_out) store_uniforms(u_out, iu0, nmine, us, (reinterpret_cast<uintptr_t>(u_out) & 15) == 0);
-    if (nmine > 0 && t == 0) uends[0] = us[0];
-#pragma unroll
-    for (int q = 0; q < kDensePer; ++q)
-        if (t * kDensePer + q == nu - 1) uends[1] = us[q];
-    lds_barrier();
+    lds_barrier();   // the block ends are in LDS
     if (!ok) {
         for (int q = 0; q < nmine; ++q) r[iu0 + q] = -1;
         if (t == 0) wide[blockIdx.x] = 0;
@@ -962,10 +960,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     }
     // global sub-tile ids of the first and the last uniform (quads 0 and 1)
     if (t < 2 * kQuad) {
-        const double xe = threshold_for(uends[(t < kQuad) ? 0 : 1], total);
+        const double xe = threshold_for(uend, total);
         const int64_t g = locate_subtile_index(wa, sbeta, kstride, ns, xe, t & (kQuad - 1));
         if ((t & (kQuad - 1)) == 0) span_ends[t / kQuad] = g;
     }
+    if (u_out) store_uniforms(u_out, iu0, nmine, us, (reinterpret_cast<uintptr_t>(u_out) & 15) == 0);
     lds_barrier();
     const int64_t gs0 = span_ends[0], gs1 = span_ends[1];
     const bool is_wide = gs1 - gs0 + 1 > static_cast<int64_t>(kWinSub) * kMaxWin;
@@ -1019,14 +1018,22 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
         const int64_t wlen64 = wa.M - ws0 * kSub;
         const int nwin = (nw * kSub < wlen64) ? nw * kSub : static_cast<int>(wlen64);
         const double wend = sw[nwin - 1];
-        // place this thread's draws that end in the window: u <= wend
-        int pos = 0;
+        // place this thread's draws that end in the window: u <= wend; the
+        // first by bisection of the window, the others galloping from it
+        int pos = -1;
 #pragma unroll
         for (int q = 0; q < kDensePer; ++q) {
             if (q >= next && q < nmine && us[q] <= wend) {
                 const double x = us[q];
-                // first j >= pos with sw[j] >= x: gallop, then bisect
-                if (sw[pos] < x) {
+                if (pos < 0) {
+                    // count of entries below x among the first nwin-1
+                    int cnt = 0;
+#pragma unroll
+                    for (int step = kWinLen / 2; step >= 1; step >>= 1)
+                        if (cnt + step <= nwin - 1 && sw[cnt + step - 1] < x) cnt += step;
+                    pos = cnt;
+                } else if (sw[pos] < x) {
+                    // first j > pos with sw[j] >= x: gallop, then bisect
                     int lo = pos, step = 1;   // sw[lo] < x
                     while (lo + step < nwin - 1 && sw[lo + step] < x) {
                         lo += step;
