@@ -205,8 +205,12 @@ def measure_batched(dcr, torch, dev, steps: int, warmup: int, cpu_seconds: float
     ws = torch.empty(dcr.dcr_batched_workspace_bytes(bw.B, w32.size, sumN, dcr.DCR_FP32_COMP),
                      dtype=torch.uint8, device=dev)
 
+    # the map tile for this batch, chosen by the library's autotuner
+    chunk, tune_ms = dcr.dcr_batched_autotune(w, w_off, n_off, seed=0, r=r, ws=ws)
+
     def step(k):
-        dcr.dcr_resample_batched(w, w_off, n_off, seed=k, r=r, dev_status=st, ws=ws)
+        dcr.dcr_resample_batched_ex(w, w_off, n_off, seed=k, chunk=chunk, r=r, dev_status=st,
+                                    ws=ws)
 
     for k in range(warmup):
         step(k)
@@ -233,6 +237,7 @@ def measure_batched(dcr, torch, dev, steps: int, warmup: int, cpu_seconds: float
     out = {
         "workload": bw.description,
         "B": bw.B, "sum_M": int(w32.size), "sum_N": sumN,
+        "map_chunk": chunk, "map_chunk_tuned_ms": tune_ms,
         "ms_per_step": ms,
         "value": sumN / (ms * 1e-3),
         "unit": "particles/s",

@@ -185,6 +185,30 @@ dcr_status dcr_resample_scheme(const void* w, int64_t M, int64_t N, uint64_t see
 dcr_status dcr_scheme_uniforms(int64_t N, uint64_t seed, uint64_t stream_id, dcr_scheme scheme,
                                double* u, hipStream_t stream);
 
+/* dcr_resample_batched with a chosen map tile: `chunk` draws of one filter
+ * per map workgroup, 256, 512 or 1024 (0: the default, 512).  The indices do
+ * not depend on it; only the speed does.  Errors: as dcr_resample_batched;
+ * DCR_ERR_UNSUPPORTED for another chunk. */
+dcr_status dcr_resample_batched_ex(const void* w, const int64_t* w_off, const int64_t* n_off,
+                                   int32_t B, int64_t sumM_max, int64_t sumN_max, uint64_t seed,
+                                   dcr_precision p, int32_t chunk, int32_t* r,
+                                   int32_t* seg_status, int32_t* dev_status, void* ws,
+                                   size_t ws_bytes, hipStream_t stream);
+
+/* Autotuner of the batched form: runs dcr_resample_batched_ex on the caller's
+ * batch with each chunk size (one untimed and three timed calls each, with HIP
+ * events on `stream`) and stores the fastest in *best_chunk (and its
+ * milliseconds per call in *best_ms if not NULL).  If `cache_path` is not NULL,
+ * a line "B sumM_max sumN_max precision chunk ms" of that file with the same
+ * shape answers without timing (*best_ms = -1), and a new result is appended.
+ * Arguments as dcr_resample_batched; r and ws are overwritten.  Unlike the
+ * other calls this one waits for the stream. */
+dcr_status dcr_batched_autotune(const void* w, const int64_t* w_off, const int64_t* n_off,
+                                int32_t B, int64_t sumM_max, int64_t sumN_max, uint64_t seed,
+                                dcr_precision p, int32_t* r, void* ws, size_t ws_bytes,
+                                const char* cache_path, int32_t* best_chunk, float* best_ms,
+                                hipStream_t stream);
+
 /* Kernel timing for measurement (not part of the sampling contract).
  * dcr_profile_begin(cap) creates HIP events for up to `cap` kernel launches;
  * every later launch records its own start and end into the next pair

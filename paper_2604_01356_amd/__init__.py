@@ -13,6 +13,7 @@ from ._binding import (  # noqa: F401
     DCR_STRATIFIED,
     DCR_SYSTEMATIC,
     DcrError,
+    dcr_batched_autotune,
     dcr_batched_workspace_bytes,
     dcr_cumulative_weights,
     dcr_inverse_cmf,
@@ -20,6 +21,7 @@ from ._binding import (  # noqa: F401
     dcr_profile_end,
     dcr_resample,
     dcr_resample_batched,
+    dcr_resample_batched_ex,
     dcr_resample_scheme,
     dcr_scheme_uniforms,
     dcr_sorted_uniforms,

@@ -66,6 +66,12 @@ def library():
     lib.dcr_resample_batched.argtypes = [P, P, P, i32, i64, i64, u64, ctypes.c_int, P, P, P, P,
                                          sz, P]
     lib.dcr_resample_batched.restype = ctypes.c_int
+    lib.dcr_resample_batched_ex.argtypes = [P, P, P, i32, i64, i64, u64, ctypes.c_int, i32, P, P,
+                                            P, P, sz, P]
+    lib.dcr_resample_batched_ex.restype = ctypes.c_int
+    lib.dcr_batched_autotune.argtypes = [P, P, P, i32, i64, i64, u64, ctypes.c_int, P, P, sz,
+                                         ctypes.c_char_p, P, P, P]
+    lib.dcr_batched_autotune.restype = ctypes.c_int
     lib.dcr_resample_scheme.argtypes = [P, i64, i64, u64, u64, ctypes.c_int, ctypes.c_int, P, P,
                                         P, P, P, sz, P]
     lib.dcr_resample_scheme.restype = ctypes.c_int
@@ -257,6 +263,57 @@ def dcr_batched_workspace_bytes(B: int, sumM_max: int, sumN_max: int,
     _check("dcr_batched_workspace_bytes", library().dcr_batched_workspace_bytes(
         int(B), int(sumM_max), int(sumN_max), int(precision), ctypes.byref(out)))
     return int(out.value)
+
+
+def _batched_args(w, w_off, n_off, sumM_max, sumN_max, r, seg_status, dev_status, ws):
+    import torch
+    _dev_tensor(w, "w")
+    _dev_tensor(w_off, "w_off", torch.int64)
+    _dev_tensor(n_off, "n_off", torch.int64)
+    B = w_off.numel() - 1
+    if n_off.numel() != B + 1:
+        raise ValueError("w_off and n_off must have the same length")
+    p = precision_of(w)
+    sumM = int(w.numel() if sumM_max is None else sumM_max)
+    if r is None:
+        if sumN_max is None:
+            raise ValueError("give r or sumN_max")
+        r = torch.empty(max(int(sumN_max), 1), dtype=torch.int32, device=w.device)
+    sumN = int(r.numel() if sumN_max is None else sumN_max)
+    _dev_tensor(r, "r", torch.int32, sumN)
+    _dev_tensor(seg_status, "seg_status", torch.int32, B)
+    _dev_tensor(dev_status, "dev_status", torch.int32, 1)
+    need = dcr_batched_workspace_bytes(B, sumM, sumN, p)
+    if ws is None:
+        ws = torch.empty(need, dtype=torch.uint8, device=w.device)
+    _dev_tensor(ws, "ws")
+    return B, p, sumM, sumN, r, ws
+
+
+def dcr_resample_batched_ex(w, w_off, n_off, seed: int, chunk: int = 0,
+                            sumM_max: int | None = None, sumN_max: int | None = None, r=None,
+                            seg_status=None, dev_status=None, ws=None):
+    """dcr_resample_batched with `chunk` draws per map workgroup (256, 512, 1024; 0: default)."""
+    B, p, sumM, sumN, r, ws = _batched_args(w, w_off, n_off, sumM_max, sumN_max, r, seg_status,
+                                            dev_status, ws)
+    _check("dcr_resample_batched_ex", library().dcr_resample_batched_ex(
+        _ptr(w), _ptr(w_off), _ptr(n_off), B, sumM, sumN, int(seed), p, int(chunk), _ptr(r),
+        _ptr(seg_status), _ptr(dev_status), _ptr(ws), ws.numel(), _stream(w.device)))
+    return r
+
+
+def dcr_batched_autotune(w, w_off, n_off, seed: int = 0, sumM_max: int | None = None,
+                         sumN_max: int | None = None, r=None, ws=None, cache_path=None):
+    """Fastest map chunk for this batch: returns (chunk, ms per call, -1 if cached)."""
+    B, p, sumM, sumN, r, ws = _batched_args(w, w_off, n_off, sumM_max, sumN_max, r, None, None,
+                                            ws)
+    best = ctypes.c_int32(0)
+    ms = ctypes.c_float(0.0)
+    _check("dcr_batched_autotune", library().dcr_batched_autotune(
+        _ptr(w), _ptr(w_off), _ptr(n_off), B, sumM, sumN, int(seed), p, _ptr(r), _ptr(ws),
+        ws.numel(), None if cache_path is None else str(cache_path).encode(),
+        ctypes.addressof(best), ctypes.addressof(ms), _stream(w.device)))
+    return int(best.value), float(ms.value)
 
 
 def dcr_resample_batched(w, w_off, n_off, seed: int, sumM_max: int | None = None,

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstdio>
 #include <vector>
 
 #include "dcr.h"
@@ -322,6 +323,8 @@ namespace {
 
 constexpr int64_t kMaxBatch = 1 << 24;
 constexpr int64_t kMaxSum = 1LL << 40;
+constexpr int kMinChunk = 256;
+constexpr int kChunks[3] = {256, 512, 1024};   // draws per map workgroup the library is built for
 
 struct BatchLayout {
     int64_t wt_cap = 0, zt_cap = 0, mc_cap = 0;
@@ -334,7 +337,7 @@ BatchLayout make_batch_layout(int64_t B, int64_t sumM, int64_t sumN) {
     BatchLayout L;
     L.wt_cap = (sumM + dcr::kBatchWBlock - 1) / dcr::kBatchWBlock + B;
     L.zt_cap = (sumN + B + dcr::kBatchZBlock - 1) / dcr::kBatchZBlock + B;
-    L.mc_cap = (sumN + dcr::kBatchChunk - 1) / dcr::kBatchChunk + B;
+    L.mc_cap = (sumN + kMinChunk - 1) / kMinChunk + B;   // the most map workgroups of any chunk
     size_t off = 0;
     auto take = [&](size_t n) {
         const size_t at_ = off;
@@ -380,6 +383,17 @@ dcr_status dcr_resample_batched(const void* w, const int64_t* w_off, const int64
                                 dcr_precision p, int32_t* r, int32_t* seg_status,
                                 int32_t* dev_status, void* ws, size_t ws_bytes,
                                 hipStream_t stream) {
+    return dcr_resample_batched_ex(w, w_off, n_off, B, sumM_max, sumN_max, seed, p, 0, r,
+                                   seg_status, dev_status, ws, ws_bytes, stream);
+}
+
+dcr_status dcr_resample_batched_ex(const void* w, const int64_t* w_off, const int64_t* n_off,
+                                   int32_t B, int64_t sumM_max, int64_t sumN_max, uint64_t seed,
+                                   dcr_precision p, int32_t chunk, int32_t* r,
+                                   int32_t* seg_status, int32_t* dev_status, void* ws,
+                                   size_t ws_bytes, hipStream_t stream) {
+    if (chunk == 0) chunk = dcr::kBatchChunkDefault;
+    if (chunk != 256 && chunk != 512 && chunk != 1024) return DCR_ERR_UNSUPPORTED;
     if (!batch_sizes_ok(B, sumM_max, sumN_max)) return DCR_ERR_INVALID_ARGUMENT;
     if (!w || !w_off || !n_off || !ws || (sumN_max > 0 && !r)) return DCR_ERR_INVALID_ARGUMENT;
     if (!valid_prec(p)) return DCR_ERR_UNSUPPORTED;
@@ -390,10 +404,11 @@ dcr_status dcr_resample_batched(const void* w, const int64_t* w_off, const int64
     ba.w_off = w_off;
     ba.n_off = n_off;
     ba.B = B;
+    ba.chunk = chunk;
     ba.seed = seed;
     ba.wt_cap = L.wt_cap;
     ba.zt_cap = L.zt_cap;
-    ba.mc_cap = L.mc_cap;
+    ba.mc_cap = (sumN_max + chunk - 1) / chunk + B;
     ba.sumM_cap = sumM_max;
     ba.sumN_cap = sumN_max;
     ba.wt_base = at<int64_t>(ws, L.wt_base);
@@ -420,6 +435,89 @@ dcr_status dcr_resample_batched(const void* w, const int64_t* w_off, const int64
         e = timed(kKBatchMap, stream,
                   [&] { return dcr::launch_map_batched(prec, w, ba, r, dev_status, stream); });
     return hip_status(e);
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner for the batched map: times each built chunk size on the caller's
+// batch and keeps the fastest, optionally cached in a text file of lines
+// "B sumM sumN precision chunk milliseconds".
+// ---------------------------------------------------------------------------
+namespace {
+
+bool cache_lookup(const char* path, int64_t B, int64_t sumM, int64_t sumN, int p, int32_t* chunk) {
+    if (!path) return false;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return false;
+    long long b, m, n;
+    int pp, c;
+    double ms;
+    bool found = false;
+    while (std::fscanf(f, "%lld %lld %lld %d %d %lf", &b, &m, &n, &pp, &c, &ms) == 6) {
+        if (b == B && m == sumM && n == sumN && pp == p &&
+            (c == 256 || c == 512 || c == 1024)) {
+            *chunk = c;   // the last entry for the key wins
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+}  // namespace
+
+dcr_status dcr_batched_autotune(const void* w, const int64_t* w_off, const int64_t* n_off,
+                                int32_t B, int64_t sumM_max, int64_t sumN_max, uint64_t seed,
+                                dcr_precision p, int32_t* r, void* ws, size_t ws_bytes,
+                                const char* cache_path, int32_t* best_chunk, float* best_ms,
+                                hipStream_t stream) {
+    if (!best_chunk) return DCR_ERR_INVALID_ARGUMENT;
+    if (cache_lookup(cache_path, B, sumM_max, sumN_max, static_cast<int>(p), best_chunk)) {
+        if (best_ms) *best_ms = -1.0f;
+        return DCR_OK;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return DCR_ERR_HIP;
+    dcr_status st = DCR_OK;
+    float best = -1.0f;
+    int32_t pick = dcr::kBatchChunkDefault;
+    constexpr int kReps = 3;
+    for (int c : kChunks) {
+        // one untimed call (also reports argument errors), then kReps timed
+        st = dcr_resample_batched_ex(w, w_off, n_off, B, sumM_max, sumN_max, seed, p, c, r,
+                                     nullptr, nullptr, ws, ws_bytes, stream);
+        if (st != DCR_OK) break;
+        if (hipEventRecord(e0, stream) != hipSuccess) { st = DCR_ERR_HIP; break; }
+        for (int k = 0; k < kReps && st == DCR_OK; ++k)
+            st = dcr_resample_batched_ex(w, w_off, n_off, B, sumM_max, sumN_max, seed, p, c, r,
+                                         nullptr, nullptr, ws, ws_bytes, stream);
+        if (st != DCR_OK) break;
+        float ms = 0.0f;
+        if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            st = DCR_ERR_HIP;
+            break;
+        }
+        ms /= kReps;
+        if (best < 0.0f || ms < best) {
+            best = ms;
+            pick = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != DCR_OK) return st;
+    *best_chunk = pick;
+    if (best_ms) *best_ms = best;
+    if (cache_path) {
+        FILE* f = std::fopen(cache_path, "a");
+        if (f) {
+            std::fprintf(f, "%lld %lld %lld %d %d %.6f\n", static_cast<long long>(B),
+                         static_cast<long long>(sumM_max), static_cast<long long>(sumN_max),
+                         static_cast<int>(p), pick, best);
+            std::fclose(f);
+        }
+    }
+    return DCR_OK;
 }
 
 dcr_status dcr_profile_begin(int32_t cap) {

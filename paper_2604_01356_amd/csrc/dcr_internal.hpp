@@ -103,12 +103,13 @@ struct BatchArgs {
     const int64_t* w_off;   // [B+1] caller's weight offsets (w_off[0] == 0)
     const int64_t* n_off;   // [B+1] caller's draw offsets (n_off[0] == 0)
     int32_t B;
+    int32_t chunk;          // draws per map workgroup: 256, 512 or 1024
     uint64_t seed;
     int64_t wt_cap, zt_cap, mc_cap;   // launch sizes: weight blocks, spacing blocks, map chunks
     int64_t sumM_cap, sumN_cap;
     int64_t* wt_base;       // [B+1] first weight block of each filter (k_batch_plan)
     int64_t* zt_base;       // [B+1] first spacing block
-    int64_t* mc_base;       // [B+1] first map chunk (512 draws)
+    int64_t* mc_base;       // [B+1] first map chunk (`chunk` draws)
     int32_t* head;          // [0] plan status, [1] batch status
     double* wt_tot;         // [wt_cap] weight-block totals
     double* wt_beta;        // [wt_cap] weight-block ends (per filter)
@@ -123,7 +124,7 @@ struct BatchArgs {
 constexpr int kPlanThreads = 1024;
 constexpr int64_t kBatchWBlock = 32768;
 constexpr int64_t kBatchZBlock = 4096;
-constexpr int64_t kBatchChunk = 512;
+constexpr int kBatchChunkDefault = 512;
 // The batched launches, in order: plan, reduce, carries, map.
 hipError_t launch_batch_plan(const BatchArgs& ba, int32_t* dev_status, hipStream_t s);
 hipError_t launch_reduce_batched(int prec, const void* w, const BatchArgs& ba, hipStream_t s);

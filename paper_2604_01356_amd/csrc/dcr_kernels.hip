@@ -1214,7 +1214,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(BatchArgs ba, int32
             } else {
                 cnt[0] = (M + kBatchWBlock - 1) / kBatchWBlock;
                 cnt[1] = (N > 0) ? (N + 1 + kBatchZBlock - 1) / kBatchZBlock : 0;
-                cnt[2] = (N + kBatchChunk - 1) / kBatchChunk;
+                cnt[2] = (N + ba.chunk - 1) / ba.chunk;
             }
         }
         // inclusive scans of the three counts (Hillis-Steele over the workgroup)
@@ -1365,14 +1365,14 @@ __global__ __launch_bounds__(kScanThreads) void k_carries_batched(BatchArgs ba) 
 // Comparisons are of unnormalised partial sums S_j with the threshold x of
 // each draw (S_j >= x  <=>  W_j >= u).  Sums follow k_reduce's order.
 // ---------------------------------------------------------------------------
-constexpr int kSegU = 512;                   // draws per workgroup
-constexpr int kSegPer = kSegU / kThreads;
+// The draws per workgroup (kSegU: 256, 512 or 1024) and the touched
+// sub-tiles per chunk pass are template parameters; the autotuner picks the
+// draws per workgroup for a batch (the result does not depend on it).
 constexpr int kSegBetaLds = 128;             // block ends kept in LDS (sampled beyond)
 constexpr int kSegSubBlocks = 4;             // blocks whose sub-tile ends are staged
-constexpr int kSegPass = 64;                 // touched sub-tiles per chunk pass
 constexpr int kSegDraws = 1;                 // draws per thread in flight at the element level
-static_assert(kBatchChunk == kSegU, "a map chunk is the draws of one k_map_batched workgroup");
 
+template <int kSegU, int kSegPass>
 struct SegLds {
     double sx[kSegU];                                  // thresholds, in draw order
     double sbeta[kSegBetaLds];
@@ -1409,9 +1409,11 @@ __device__ __forceinline__ int64_t seg_block_of(const WArgs& wa, const double* s
     return blo;
 }
 
-template <typename Tin>
+template <typename Tin, int kSegU, int kSegPass>
 __device__ void map_seg_chunk(const Tin* __restrict__ w, const WArgs& wa, const ZArgs& za,
-                              const SharedArgs& sh, int32_t* __restrict__ r, int64_t c, SegLds& L) {
+                              const SharedArgs& sh, int32_t* __restrict__ r, int64_t c,
+                              SegLds<kSegU, kSegPass>& L) {
+    constexpr int kSegPer = kSegU / kThreads;
     const int t = threadIdx.x;
     const int64_t N = za.N;
     const int64_t i0 = c * kSegU;
@@ -1674,11 +1676,11 @@ __device__ void map_seg_chunk(const Tin* __restrict__ w, const WArgs& wa, const 
 }
 
 // kSegU draws of one filter per workgroup; indices are local to the filter.
-template <typename Tin>
+template <typename Tin, int kSegU, int kSegPass>
 __global__ __launch_bounds__(kThreads) void k_map_batched(const Tin* __restrict__ w, BatchArgs ba,
                                                           int32_t* __restrict__ r,
                                                           int32_t* dev_status) {
-    __shared__ SegLds L;
+    __shared__ SegLds<kSegU, kSegPass> L;
     const int plan = ba.head[0];
     if (blockIdx.x == 0 && threadIdx.x == 0 && dev_status)
         *dev_status = (plan != kStatusOk) ? plan : ba.head[1];
@@ -1687,7 +1689,7 @@ __global__ __launch_bounds__(kThreads) void k_map_batched(const Tin* __restrict_
     if (c >= ba.mc_base[ba.B]) return;
     const int b = find_segment(ba.mc_base, ba.B, c);
     const Tin* ws = w + ba.w_off[b];
-    map_seg_chunk<Tin>(ws, seg_wargs(ba, b), seg_zargs(ba, b), seg_shared(ba, b),
+    map_seg_chunk<Tin, kSegU, kSegPass>(ws, seg_wargs(ba, b), seg_zargs(ba, b), seg_shared(ba, b),
                        r + ba.n_off[b], c - ba.mc_base[b], L);
 }
 
@@ -1862,15 +1864,25 @@ hipError_t launch_carries_batched(const BatchArgs& ba, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <typename Tin>
+static void launch_map_batched_t(const Tin* w, const BatchArgs& ba, int32_t* r, int32_t* dev_status,
+                                 hipStream_t s) {
+    const unsigned grid = static_cast<unsigned>(ba.mc_cap);
+    if (ba.chunk == 256)
+        launch(k_map_batched<Tin, 256, 32>, dim3(grid), dim3(kThreads), 0, s, w, ba, r, dev_status);
+    else if (ba.chunk == 1024)
+        launch(k_map_batched<Tin, 1024, 64>, dim3(grid), dim3(kThreads), 0, s, w, ba, r, dev_status);
+    else
+        launch(k_map_batched<Tin, 512, 64>, dim3(grid), dim3(kThreads), 0, s, w, ba, r, dev_status);
+}
+
 hipError_t launch_map_batched(int prec, const void* w, const BatchArgs& ba, int32_t* r,
                               int32_t* dev_status, hipStream_t s) {
-    const unsigned grid = static_cast<unsigned>(ba.mc_cap);
+    if (ba.chunk != 256 && ba.chunk != 512 && ba.chunk != 1024) return hipErrorInvalidValue;
     if (prec == kPrecFP32)
-        launch(k_map_batched<float>, dim3(grid), dim3(kThreads), 0, s, static_cast<const float*>(w),
-               ba, r, dev_status);
+        launch_map_batched_t(static_cast<const float*>(w), ba, r, dev_status, s);
     else
-        launch(k_map_batched<double>, dim3(grid), dim3(kThreads), 0, s,
-               static_cast<const double*>(w), ba, r, dev_status);
+        launch_map_batched_t(static_cast<const double*>(w), ba, r, dev_status, s);
     return hipGetLastError();
 }
 

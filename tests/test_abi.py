@@ -141,6 +141,12 @@ def test_host_validation_batched(lib):
     assert call(ws=FAKE_UNALIGNED) == 1
     assert call(p=4) == 2
     assert call(ws_bytes=ws - 1) == 3
+    # the tuned form rejects a map tile it is not built for, before any launch
+    ex = lib.dcr_resample_batched_ex
+    assert ex(FAKE, FAKE, FAKE, 8, 1000, 100, 1, 1, 100, FAKE, None, None, FAKE, ws, None) == 2
+    assert ex(FAKE, FAKE, FAKE, 8, 1000, 100, 1, 1, 512, FAKE, None, None, FAKE, 16, None) == 3
+    at = lib.dcr_batched_autotune
+    assert at(FAKE, FAKE, FAKE, 8, 1000, 100, 1, 1, FAKE, FAKE, ws, None, None, None, None) == 1
 
 
 def test_host_validation_schemes(lib):

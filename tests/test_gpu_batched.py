@@ -197,3 +197,26 @@ def test_batched_full_size_sampled(dcr, dev):
             assert part[0] >= 0 and part[-1] < Mb[b] and np.all(np.diff(part) >= 0)
     print(f"  batched B={bw.B} sumM={int(bw.w_off[-1])} sumN={int(bw.n_off[-1])}: "
           f"{mism} bin-edge mismatches in {len(pick)} sampled filters")
+
+
+def test_batched_chunks_agree_and_autotune(dcr, dev, tmp_path):
+    """Every map tile gives the same indices; the autotuner picks one of them
+    and answers from its cache the second time."""
+    w, w_off, n_off = small_batch(50, 16, empty_every=9)
+    w = w.astype(np.float32)
+    wt, wo, no = _t(w, dev), _t(w_off, dev), _t(n_off, dev)
+    n = int(n_off[-1])
+    outs = {}
+    for c in (256, 512, 1024):
+        r = dcr.dcr_resample_batched_ex(wt, wo, no, 6, chunk=c, sumN_max=n)
+        torch.cuda.synchronize()
+        outs[c] = r.cpu().numpy()[:n]
+    assert np.array_equal(outs[256], outs[512]) and np.array_equal(outs[512], outs[1024])
+    ref = oracle.resample_batched(w, w_off, n_off, 6)
+    mism = int(np.sum(outs[512] != ref))
+    assert mism <= max(10, n // 1000)          # binary32 form: bin-edge cases only
+    cache = tmp_path / "tune.txt"
+    c1, ms1 = dcr.dcr_batched_autotune(wt, wo, no, 6, sumN_max=n, cache_path=cache)
+    assert c1 in (256, 512, 1024) and ms1 > 0
+    c2, ms2 = dcr.dcr_batched_autotune(wt, wo, no, 6, sumN_max=n, cache_path=cache)
+    assert c2 == c1 and ms2 == -1.0
