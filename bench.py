@@ -308,6 +308,8 @@ def main():
     ap.add_argument("--workload", default="sparse", choices=["sparse", "equal", "engmf", "single"])
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 4096-filter batched workload reported beside the main line")
+    ap.add_argument("--no-equal", action="store_true",
+                    help="skip the equal-size workload reported beside the main line")
     ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
     ap.add_argument("--no-compare", action="store_true", help="skip the other precision")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -470,6 +472,16 @@ def main():
     if not args.no_batched:
         out["batched"] = measure_batched(dcr, torch, dev, max(5, args.steps // 5), 2,
                                          0.0 if args.no_cpu else args.cpu_seconds / 2)
+    if args.workload != "equal" and not args.no_equal:
+        # the equal-size instance (linear-merge limit of the map), binary32 form
+        wl_eq = workloads.CONFIGS["equal"]()
+        wl_saved = wl
+        wl = wl_eq
+        ms_e, kern_e, _, _, _ = measure("f32", max(5, args.steps // 5), 2)
+        wl = wl_saved
+        out["equal"] = {"workload": wl_eq.description, "ms_per_step": ms_e,
+                        "value": wl_eq.N / (ms_e * 1e-3), "unit": "particles/s",
+                        "kernels_ms": kern_e}
     print(json.dumps(out), flush=True)
 
 

@@ -136,6 +136,25 @@ def test_counts_chi_square_gpu(dev, dcr):
     assert stats.chisquare(c, N * w / w.sum()).pvalue > 1e-4
 
 
+@pytest.mark.parametrize("M,N", [(3000, 50000), (200000, 2000)])
+def test_counts_chi_square_regimes_gpu(dev, dcr, M, N):
+    """Counts pooled over seeds against N w (chi square on cells with at
+    least 20 expected draws), in the dense merge and in the sparse map."""
+    rng = np.random.default_rng(M)
+    w = np.exp(rng.normal(0, 1.5, M))
+    p = w / w.sum()
+    R = 30
+    wt = _t(w, dev)
+    c = np.zeros(M)
+    for s in range(R):
+        c += np.bincount(dcr.dcr_resample(wt, N, seed=1000 + s).cpu().numpy(), minlength=M)
+    exp = R * N * p
+    big = exp >= 20
+    obs = np.concatenate([c[big], [c[~big].sum()]])
+    ex = np.concatenate([exp[big], [exp[~big].sum()]])
+    assert stats.chisquare(obs, ex).pvalue > 1e-4
+
+
 def test_seed_and_stream_reproducible(dev, dcr):
     w = _t(np.exp(np.random.default_rng(1).normal(0, 1, 10000)), dev)
     a = dcr.dcr_resample(w, 3000, seed=5, stream_id=2).cpu().numpy()
