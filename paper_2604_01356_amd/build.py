@@ -25,7 +25,7 @@ def hipcc_path() -> str:
 def compile_flags() -> list[str]:
     return [
         f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
-        "-ffp-contract=off",
+        "-ffp-contract=off", "-Wall",
         # packed binary32 vector ops stay off: some of their forms have given
         # wrong results on this chip
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

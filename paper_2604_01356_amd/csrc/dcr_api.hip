@@ -159,6 +159,88 @@ dcr_status hip_status(hipError_t e) { return e == hipSuccess ? DCR_OK : DCR_ERR_
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Batched form
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int64_t kMaxBatch = 1 << 24;
+constexpr int64_t kMaxSum = 1LL << 40;
+constexpr int kMinChunk = 256;
+constexpr int kChunks[3] = {256, 512, 1024};   // draws per map workgroup the library is built for
+
+struct BatchLayout {
+    int64_t wt_cap = 0, zt_cap = 0, mc_cap = 0;
+    size_t head = 0, wt_base = 0, zt_base = 0, mc_base = 0, seg_status = 0, seg_totals = 0;
+    size_t wt_tot = 0, wt_beta = 0, wt_sub = 0, wt_chunk = 0, zt_tot = 0, zt_beta = 0, zrel = 0;
+    size_t bytes = 0;
+};
+
+BatchLayout make_batch_layout(int64_t B, int64_t sumM, int64_t sumN) {
+    BatchLayout L;
+    L.wt_cap = (sumM + dcr::kBatchWBlock - 1) / dcr::kBatchWBlock + B;
+    L.zt_cap = (sumN + B + dcr::kBatchZBlock - 1) / dcr::kBatchZBlock + B;
+    L.mc_cap = (sumN + kMinChunk - 1) / kMinChunk + B;   // the most map workgroups of any chunk
+    size_t off = 0;
+    auto take = [&](size_t n) {
+        const size_t at_ = off;
+        off = align256(off + n);
+        return at_;
+    };
+    L.head = take(256);
+    L.wt_base = take(sizeof(int64_t) * (B + 1));
+    L.zt_base = take(sizeof(int64_t) * (B + 1));
+    L.mc_base = take(sizeof(int64_t) * (B + 1));
+    L.seg_status = take(sizeof(int32_t) * B);
+    L.seg_totals = take(sizeof(double) * 2 * B);
+    L.wt_tot = take(sizeof(double) * L.wt_cap);
+    L.wt_beta = take(sizeof(double) * L.wt_cap);
+    L.wt_sub = take(sizeof(double) * L.wt_cap * kWSubPerBlock);
+    L.wt_chunk = take(sizeof(double) * L.wt_cap * kWSubPerBlock * 16);
+    L.zt_tot = take(sizeof(double) * L.zt_cap);
+    L.zt_beta = take(sizeof(double) * L.zt_cap);
+    L.zrel = take(sizeof(double) * (sumN + B));
+    L.bytes = off;
+    return L;
+}
+
+bool batch_sizes_ok(int64_t B, int64_t sumM, int64_t sumN) {
+    if (B < 1 || B > kMaxBatch || sumM < B || sumM > kMaxSum || sumN < 0 || sumN > kMaxSum)
+        return false;
+    const BatchLayout L = make_batch_layout(B, sumM, sumN);
+    return L.wt_cap + L.zt_cap <= 0x7FFFFFFF && L.mc_cap <= 0x7FFFFFFF;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Autotuner for the batched map: times each built chunk size on the caller's
+// batch and keeps the fastest, optionally cached in a text file of lines
+// "B sumM sumN precision chunk milliseconds".
+// ---------------------------------------------------------------------------
+namespace {
+
+bool cache_lookup(const char* path, int64_t B, int64_t sumM, int64_t sumN, int p, int32_t* chunk) {
+    if (!path) return false;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return false;
+    long long b, m, n;
+    int pp, c;
+    double ms;
+    bool found = false;
+    while (std::fscanf(f, "%lld %lld %lld %d %d %lf", &b, &m, &n, &pp, &c, &ms) == 6) {
+        if (b == B && m == sumM && n == sumN && pp == p &&
+            (c == 256 || c == 512 || c == 1024)) {
+            *chunk = c;   // the last entry for the key wins
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* dcr_status_string(dcr_status s) {
@@ -302,7 +384,7 @@ dcr_status dcr_resample_scheme(const void* w, int64_t M, int64_t N, uint64_t see
     if (e == hipSuccess && N > 0) {
         if (dcr::map_is_dense(M, N)) {
             e = timed(kKMapDense, stream, [&] {
-                return dcr::launch_map_dense(prec, w, wa, za, sh, u_opt, r, wide, vec, stream);
+                return dcr::launch_map_dense(prec, w, wa, za, sh, u_opt, r, wide, stream);
             });
             if (e == hipSuccess)
                 e = timed(kKMapWide, stream, [&] {
@@ -316,59 +398,6 @@ dcr_status dcr_resample_scheme(const void* w, int64_t M, int64_t N, uint64_t see
     return hip_status(e);
 }
 
-// ---------------------------------------------------------------------------
-// Batched form
-// ---------------------------------------------------------------------------
-namespace {
-
-constexpr int64_t kMaxBatch = 1 << 24;
-constexpr int64_t kMaxSum = 1LL << 40;
-constexpr int kMinChunk = 256;
-constexpr int kChunks[3] = {256, 512, 1024};   // draws per map workgroup the library is built for
-
-struct BatchLayout {
-    int64_t wt_cap = 0, zt_cap = 0, mc_cap = 0;
-    size_t head = 0, wt_base = 0, zt_base = 0, mc_base = 0, seg_status = 0, seg_totals = 0;
-    size_t wt_tot = 0, wt_beta = 0, wt_sub = 0, wt_chunk = 0, zt_tot = 0, zt_beta = 0, zrel = 0;
-    size_t bytes = 0;
-};
-
-BatchLayout make_batch_layout(int64_t B, int64_t sumM, int64_t sumN) {
-    BatchLayout L;
-    L.wt_cap = (sumM + dcr::kBatchWBlock - 1) / dcr::kBatchWBlock + B;
-    L.zt_cap = (sumN + B + dcr::kBatchZBlock - 1) / dcr::kBatchZBlock + B;
-    L.mc_cap = (sumN + kMinChunk - 1) / kMinChunk + B;   // the most map workgroups of any chunk
-    size_t off = 0;
-    auto take = [&](size_t n) {
-        const size_t at_ = off;
-        off = align256(off + n);
-        return at_;
-    };
-    L.head = take(256);
-    L.wt_base = take(sizeof(int64_t) * (B + 1));
-    L.zt_base = take(sizeof(int64_t) * (B + 1));
-    L.mc_base = take(sizeof(int64_t) * (B + 1));
-    L.seg_status = take(sizeof(int32_t) * B);
-    L.seg_totals = take(sizeof(double) * 2 * B);
-    L.wt_tot = take(sizeof(double) * L.wt_cap);
-    L.wt_beta = take(sizeof(double) * L.wt_cap);
-    L.wt_sub = take(sizeof(double) * L.wt_cap * kWSubPerBlock);
-    L.wt_chunk = take(sizeof(double) * L.wt_cap * kWSubPerBlock * 16);
-    L.zt_tot = take(sizeof(double) * L.zt_cap);
-    L.zt_beta = take(sizeof(double) * L.zt_cap);
-    L.zrel = take(sizeof(double) * (sumN + B));
-    L.bytes = off;
-    return L;
-}
-
-bool batch_sizes_ok(int64_t B, int64_t sumM, int64_t sumN) {
-    if (B < 1 || B > kMaxBatch || sumM < B || sumM > kMaxSum || sumN < 0 || sumN > kMaxSum)
-        return false;
-    const BatchLayout L = make_batch_layout(B, sumM, sumN);
-    return L.wt_cap + L.zt_cap <= 0x7FFFFFFF && L.mc_cap <= 0x7FFFFFFF;
-}
-
-}  // namespace
 
 dcr_status dcr_batched_workspace_bytes(int32_t B, int64_t sumM_max, int64_t sumN_max,
                                        dcr_precision p, size_t* bytes) {
@@ -437,33 +466,6 @@ dcr_status dcr_resample_batched_ex(const void* w, const int64_t* w_off, const in
     return hip_status(e);
 }
 
-// ---------------------------------------------------------------------------
-// Autotuner for the batched map: times each built chunk size on the caller's
-// batch and keeps the fastest, optionally cached in a text file of lines
-// "B sumM sumN precision chunk milliseconds".
-// ---------------------------------------------------------------------------
-namespace {
-
-bool cache_lookup(const char* path, int64_t B, int64_t sumM, int64_t sumN, int p, int32_t* chunk) {
-    if (!path) return false;
-    FILE* f = std::fopen(path, "r");
-    if (!f) return false;
-    long long b, m, n;
-    int pp, c;
-    double ms;
-    bool found = false;
-    while (std::fscanf(f, "%lld %lld %lld %d %d %lf", &b, &m, &n, &pp, &c, &ms) == 6) {
-        if (b == B && m == sumM && n == sumN && pp == p &&
-            (c == 256 || c == 512 || c == 1024)) {
-            *chunk = c;   // the last entry for the key wins
-            found = true;
-        }
-    }
-    std::fclose(f);
-    return found;
-}
-
-}  // namespace
 
 dcr_status dcr_batched_autotune(const void* w, const int64_t* w_off, const int64_t* n_off,
                                 int32_t B, int64_t sumM_max, int64_t sumN_max, uint64_t seed,

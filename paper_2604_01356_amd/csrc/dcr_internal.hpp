@@ -74,7 +74,7 @@ int64_t dense_chunks(int64_t M, int64_t N);   // at most ceil(N / 256)
 // launch_map_wide then places the draws of the flagged chunks.
 hipError_t launch_map_dense(int prec, const void* w, const WArgs& wa, const ZArgs& za,
                             const SharedArgs& sh, double* u_out, int32_t* r, int32_t* wide,
-                            int vec_ok, hipStream_t s);
+                            hipStream_t s);
 // the flagged (wide-span) chunks left by launch_map_dense
 hipError_t launch_map_wide(int prec, const void* w, const WArgs& wa, const ZArgs& za,
                            const SharedArgs& sh, int32_t* r, const int32_t* wide, int vec_ok,

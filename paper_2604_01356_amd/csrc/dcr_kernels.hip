@@ -896,8 +896,7 @@ template <typename Tin>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_map_dense(const Tin* __restrict__ w, WArgs wa, ZArgs za,
                                                         SharedArgs sh, double* __restrict__ u_out,
                                                         int32_t* __restrict__ r,
-                                                        int32_t* __restrict__ wide, int vec_ok,
-                                                        int per_wg) {
+                                                        int32_t* __restrict__ wide, int per_wg) {
     // block ends for the search of the span, then a window of normalised
     // cumulative weights
     __shared__ double lds[kBetaLds];
@@ -1783,16 +1782,16 @@ int64_t dense_chunks(int64_t M, int64_t N) {
 
 hipError_t launch_map_dense(int prec, const void* w, const WArgs& wa, const ZArgs& za,
                             const SharedArgs& sh, double* u_out, int32_t* r, int32_t* wide,
-                            int vec_ok, hipStream_t s) {
+                            hipStream_t s) {
     if (za.N <= 0) return hipSuccess;
     const int per = dense_per_wg(wa.M, za.N);
     const int64_t grid = dense_chunks(wa.M, za.N);
     if (prec == kPrecFP32)
         launch(k_map_dense<float>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s,
-               static_cast<const float*>(w), wa, za, sh, u_out, r, wide, vec_ok, per);
+               static_cast<const float*>(w), wa, za, sh, u_out, r, wide, per);
     else
         launch(k_map_dense<double>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s,
-               static_cast<const double*>(w), wa, za, sh, u_out, r, wide, vec_ok, per);
+               static_cast<const double*>(w), wa, za, sh, u_out, r, wide, per);
     return hipGetLastError();
 }
 

@@ -200,3 +200,31 @@ def test_full_size(dev, dcr, which, dtype):
     du_cap = 1e-12 if dtype == "f64" else DU_FP32
     n_mis = check_against_oracle(out, w, N, 0, 0, du_cap, 2.0**-40)
     assert n_mis <= max(10, N // 1000)
+
+
+def test_large_n_dense(dev, dcr):
+    """N = 2^26 draws from M = 2^22 binary32 weights (16 draws per weight, the
+    dense merge, 64-bit draw offsets in the grid): u is sorted and agrees with
+    the oracle's within the binary32 bound, r is non-decreasing, and sampled
+    indices are exact on the GPU's own W and u."""
+    M, N = 1 << 22, 1 << 26
+    rng = np.random.default_rng(2026)
+    w = np.exp(rng.normal(0, 1, M)).astype(np.float32)
+    wt = _t(w, dev)
+    W = torch.empty(M, dtype=torch.float64, device=dev)
+    u = torch.empty(N, dtype=torch.float64, device=dev)
+    st = torch.full((1,), -1, dtype=torch.int32, device=dev)
+    r = dcr.dcr_resample(wt, N, seed=3, stream_id=7, W_out=W, u_out=u, dev_status=st)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    rg, Wg, ug = r.cpu().numpy(), W.cpu().numpy(), u.cpu().numpy()
+    del r, W, u
+    assert_monotone_unit(Wg)
+    assert np.all(np.diff(ug) >= 0) and ug[0] > 0 and ug[-1] <= 1
+    assert np.all(np.diff(rg) >= 0) and rg[0] >= 0 and rg[-1] < M
+    idx = np.unique(np.concatenate([np.arange(0, N, 4099), [N - 1]]))
+    j = rg[idx]
+    assert np.all(Wg[j] >= ug[idx])
+    assert np.all((j == 0) | (Wg[np.maximum(j - 1, 0)] < ug[idx]))
+    u_o = oracle.sorted_uniforms(N, 3, 7, zkind=1)
+    assert np.max(np.abs(ug - u_o)) <= DU_FP32
