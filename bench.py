@@ -59,7 +59,7 @@ def source_digest(kernel: str) -> str:
     use is defined above it), so later kernels do not change it."""
     csrc = os.path.join(ROOT, "paper_2604_01356_amd", "csrc")
     h = hashlib.sha256()
-    for name in ("dcr_device.hpp", "dcr_internal.hpp"):
+    for name in ("dcr_device.hpp", "dcr_internal.hpp"):   # what the kernels are built from
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(f.read())
     with open(KERNEL_SOURCE, "r") as f:

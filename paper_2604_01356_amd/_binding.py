@@ -45,7 +45,7 @@ def library():
         return _lib
     if not os.path.exists(_LIB_PATH):
         raise ImportError(
-            f"{_LIB_PATH} is not built; run `python -c 'import __graft_entry__ as g; g.build()'`")
+            f"{_LIB_PATH} is not built; run `python paper_2604_01356_amd/build.py`")
     lib = ctypes.CDLL(_LIB_PATH)
     P, i64, u64, i32, sz = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_int32,
                             ctypes.c_size_t)

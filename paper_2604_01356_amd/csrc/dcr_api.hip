@@ -9,6 +9,7 @@
 
 #include "dcr.h"
 #include "dcr_internal.hpp"
+#include "dcr_launch.hpp"
 
 namespace dcr {
 LaunchEvents g_launch_events;

@@ -1,5 +1,6 @@
-// dcr_internal.hpp -- argument blocks and launchers shared by the host API and
-// the kernels of libdcr.  Not part of the public C ABI.
+// dcr_internal.hpp -- argument blocks and constants shared by the host API and
+// the kernels of libdcr (the launchers are in dcr_launch.hpp).  Not part of
+// the public C ABI.
 #pragma once
 
 #include <hip/hip_runtime_api.h>
@@ -7,15 +8,6 @@
 
 namespace dcr {
 
-// Optional timing of the next kernel launch: when `start` and `stop` are set,
-// the launch records its own start and end into them (hipExtLaunchKernel), so
-// the interval is the kernel alone.  `launches` counts every launch made.
-struct LaunchEvents {
-    hipEvent_t start = nullptr;
-    hipEvent_t stop = nullptr;
-    int64_t launches = 0;
-};
-extern LaunchEvents g_launch_events;
 
 constexpr int kPrecFP64 = 0;
 constexpr int kPrecFP32 = 1;
@@ -57,42 +49,13 @@ struct SharedArgs {
     double* totals;    // [2] weight total, spacing total
 };
 
-hipError_t launch_reduce(int prec, const void* w, const WArgs& wa, const ZArgs& za, int vec_ok,
-                         hipStream_t s);
 // k_finish handles up to 4096 weight blocks (M <= 2^27) and this many
 // spacing blocks (N + 1 <= 2^18).
 constexpr int kFinishMaxZBlocks = 64;
-bool finish_fits(const WArgs& wa, const ZArgs& za);
 
 // N * kDenseRatio >= M: several uniforms per sub-tile on average, mapped by
 // the windowed linear merge (k_map_dense) instead of one search per uniform.
 constexpr int64_t kDenseRatio = 4;
-bool map_is_dense(int64_t M, int64_t N);
-int64_t dense_chunks(int64_t M, int64_t N);   // at most ceil(N / 256)
-// k_map_dense: merges each chunk of 4096 draws and flags in `wide`
-// (dense_chunks(M, N) int32 flags) the chunks whose span is too wide to merge;
-// launch_map_wide then places the draws of the flagged chunks.
-hipError_t launch_map_dense(int prec, const void* w, const WArgs& wa, const ZArgs& za,
-                            const SharedArgs& sh, double* u_out, int32_t* r, int32_t* wide,
-                            hipStream_t s);
-// the flagged (wide-span) chunks left by launch_map_dense
-hipError_t launch_map_wide(int prec, const void* w, const WArgs& wa, const ZArgs& za,
-                           const SharedArgs& sh, int32_t* r, const int32_t* wide, int vec_ok,
-                           hipStream_t s);
-
-hipError_t launch_carries(const WArgs& wa, const ZArgs& za, const SharedArgs& sh,
-                          int32_t* dev_status, double* total_out, hipStream_t s);
-hipError_t launch_finish(int prec, const void* w, const WArgs& wa, const ZArgs& za,
-                         const SharedArgs& sh, int32_t* dev_status, double* u_out, int32_t* r,
-                         int vec_ok, hipStream_t s);
-hipError_t launch_materialize_w(int prec, const void* w, const WArgs& wa, const SharedArgs& sh,
-                                double* W, int vec_ok, hipStream_t s);
-hipError_t launch_materialize_u(const ZArgs& za, const SharedArgs& sh, double* u, hipStream_t s);
-hipError_t launch_map_fused(int prec, const void* w, const WArgs& wa, const ZArgs& za,
-                            const SharedArgs& sh, double* u_out, int32_t* r, int vec_ok,
-                            hipStream_t s);
-hipError_t launch_map_w(const double* W, int64_t M, const double* u, int64_t N, int32_t* r,
-                        hipStream_t s);
 
 // Batched form: B independent filters over concatenated arrays.  Filter b
 // owns weights [w_off[b], w_off[b+1]) and draws [n_off[b], n_off[b+1]); its
@@ -125,11 +88,4 @@ constexpr int kPlanThreads = 1024;
 constexpr int64_t kBatchWBlock = 32768;
 constexpr int64_t kBatchZBlock = 4096;
 constexpr int kBatchChunkDefault = 512;
-// The batched launches, in order: plan, reduce, carries, map.
-hipError_t launch_batch_plan(const BatchArgs& ba, int32_t* dev_status, hipStream_t s);
-hipError_t launch_reduce_batched(int prec, const void* w, const BatchArgs& ba, hipStream_t s);
-hipError_t launch_carries_batched(const BatchArgs& ba, hipStream_t s);
-hipError_t launch_map_batched(int prec, const void* w, const BatchArgs& ba, int32_t* r,
-                              int32_t* dev_status, hipStream_t s);
-
 }  // namespace dcr

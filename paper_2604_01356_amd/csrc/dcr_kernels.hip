@@ -23,6 +23,7 @@
 
 #include "dcr_device.hpp"
 #include "dcr_internal.hpp"
+#include "dcr_launch.hpp"
 
 namespace dcr {
 

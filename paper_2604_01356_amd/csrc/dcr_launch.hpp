@@ -1,0 +1,60 @@
+// dcr_launch.hpp -- host-side launchers of the libdcr kernels and the optional
+// per-launch timing hook.  Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+#include "dcr_internal.hpp"
+
+namespace dcr {
+
+// Optional timing of the next kernel launch: when `start` and `stop` are set,
+// the launch records its own start and end into them (hipExtLaunchKernel), so
+// the interval is the kernel alone.  `launches` counts every launch made.
+struct LaunchEvents {
+    hipEvent_t start = nullptr;
+    hipEvent_t stop = nullptr;
+    int64_t launches = 0;
+};
+extern LaunchEvents g_launch_events;
+
+hipError_t launch_reduce(int prec, const void* w, const WArgs& wa, const ZArgs& za, int vec_ok,
+                         hipStream_t s);
+bool finish_fits(const WArgs& wa, const ZArgs& za);
+
+bool map_is_dense(int64_t M, int64_t N);
+int64_t dense_chunks(int64_t M, int64_t N);   // at most ceil(N / 256)
+// k_map_dense: merges each chunk of draws and flags in `wide`
+// (dense_chunks(M, N) int32 flags) the chunks whose span is too wide to merge;
+// launch_map_wide then places the draws of the flagged chunks.
+hipError_t launch_map_dense(int prec, const void* w, const WArgs& wa, const ZArgs& za,
+                            const SharedArgs& sh, double* u_out, int32_t* r, int32_t* wide,
+                            hipStream_t s);
+// the flagged (wide-span) chunks left by launch_map_dense
+hipError_t launch_map_wide(int prec, const void* w, const WArgs& wa, const ZArgs& za,
+                           const SharedArgs& sh, int32_t* r, const int32_t* wide, int vec_ok,
+                           hipStream_t s);
+
+hipError_t launch_carries(const WArgs& wa, const ZArgs& za, const SharedArgs& sh,
+                          int32_t* dev_status, double* total_out, hipStream_t s);
+hipError_t launch_finish(int prec, const void* w, const WArgs& wa, const ZArgs& za,
+                         const SharedArgs& sh, int32_t* dev_status, double* u_out, int32_t* r,
+                         int vec_ok, hipStream_t s);
+hipError_t launch_materialize_w(int prec, const void* w, const WArgs& wa, const SharedArgs& sh,
+                                double* W, int vec_ok, hipStream_t s);
+hipError_t launch_materialize_u(const ZArgs& za, const SharedArgs& sh, double* u, hipStream_t s);
+hipError_t launch_map_fused(int prec, const void* w, const WArgs& wa, const ZArgs& za,
+                            const SharedArgs& sh, double* u_out, int32_t* r, int vec_ok,
+                            hipStream_t s);
+hipError_t launch_map_w(const double* W, int64_t M, const double* u, int64_t N, int32_t* r,
+                        hipStream_t s);
+
+// The batched launches, in order: plan, reduce, carries, map.
+hipError_t launch_batch_plan(const BatchArgs& ba, int32_t* dev_status, hipStream_t s);
+hipError_t launch_reduce_batched(int prec, const void* w, const BatchArgs& ba, hipStream_t s);
+hipError_t launch_carries_batched(const BatchArgs& ba, hipStream_t s);
+hipError_t launch_map_batched(int prec, const void* w, const BatchArgs& ba, int32_t* r,
+                              int32_t* dev_status, hipStream_t s);
+
+}  // namespace dcr
