@@ -177,6 +177,23 @@ dcr_status dcr_resample_scheme(const void* w, int64_t M, int64_t N, uint64_t see
                                double* W_opt, double* u_opt, int32_t* dev_status, void* ws,
                                size_t ws_bytes, hipStream_t stream);
 
+/* End to end on structured weights (the ensemble Gaussian mixture filter of
+ * Sec. IV: particle i, likelihood component k): M = Na * P weights
+ *   w_{i*P + k} = a[i] * b[k],   i < Na, k < P,
+ * formed on the fly as binary64 products (exact for DCR_FP32_COMP, whose a and
+ * b are binary32) and never read from memory.  Everything else is as
+ * dcr_resample_scheme on the weight array w: the same W, u and r as that call
+ * on the materialised products with the same precision form.
+ *   a [Na], b [P]   device arrays of the precision's type, non-negative.
+ *   ws              dcr_workspace_bytes(Na * P, N, p) bytes.
+ * Errors: as dcr_resample_scheme; DCR_ERR_INVALID_ARGUMENT for Na < 1, P < 1,
+ * Na * P > 2^31 - 1 or NULL a, b. */
+dcr_status dcr_resample_outer(const void* a, int64_t Na, const void* b, int64_t P, int64_t N,
+                              uint64_t seed, uint64_t stream_id, dcr_precision p,
+                              dcr_scheme scheme, int32_t* r, double* W_opt, double* u_opt,
+                              int32_t* dev_status, void* ws, size_t ws_bytes,
+                              hipStream_t stream);
+
 /* The uniforms of the stratified or systematic scheme alone:
  *   u        [N] binary64 out, non-decreasing, in (0, 1]; needs no workspace.
  * Errors: DCR_ERR_INVALID_ARGUMENT (N out of range, u NULL with N > 0),

@@ -74,6 +74,8 @@ def _load():
     lib.dcro_dac.restype = i64
     lib.dcro_resample.argtypes = [P, i64, i64, u64, u64, P, P, P]
     lib.dcro_resample.restype = i32
+    lib.dcro_resample_z.argtypes = [P, i64, i64, u64, u64, i32, P, P, P]
+    lib.dcro_resample_z.restype = i32
     lib.dcro_resample_f32.argtypes = [P, i64, i64, u64, u64, i32, P, P, P]
     lib.dcro_resample_f32.restype = i32
     lib.dcro_resample_repeat.argtypes = [P, i64, i64, u64, i64, P]
@@ -229,7 +231,8 @@ def resample(w: np.ndarray, N: int, seed: int, stream: int = 0, zkind: int | Non
     """DaC sampler end to end: returns (r, W, u).
 
     binary32 weights are promoted exactly; zkind selects the spacings form
-    (default: 0 for binary64 weights, 1 for binary32 weights).
+    (default: 0 for binary64 weights, 1 for binary32 weights; binary64 weights
+    may take zkind 1, the form the binary32 outer-product path uses).
     """
     w = np.ascontiguousarray(w)
     M = w.shape[0]
@@ -241,10 +244,9 @@ def resample(w: np.ndarray, N: int, seed: int, stream: int = 0, zkind: int | Non
         zk = 1 if zkind is None else zkind
         st = lib.dcro_resample_f32(_ptr(w), M, N, seed, stream, zk, _ptr(r), _ptr(W), _ptr(u))
     else:
-        if zkind not in (None, 0):
-            raise ValueError("binary64 weights use zkind 0")
         w = _f64(w)
-        st = lib.dcro_resample(_ptr(w), M, N, seed, stream, _ptr(r), _ptr(W), _ptr(u))
+        st = lib.dcro_resample_z(_ptr(w), M, N, seed, stream, 0 if zkind is None else zkind,
+                                 _ptr(r), _ptr(W), _ptr(u))
     if st != OK:
         raise OracleError(f"resample: status {st}")
     return r[:N], W, u[:N]

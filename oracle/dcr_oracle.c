@@ -332,6 +332,14 @@ int dcro_resample(const double* w, int64_t M, int64_t N, uint64_t seed, uint64_t
     return resample_impl(w, 0, M, N, seed, stream, 0, r, W_out, u_out);
 }
 
+/* binary64 weights with a chosen spacings form (zkind 1: the binary32 form,
+ * as used when binary32 factors give exact binary64 product weights). */
+int dcro_resample_z(const double* w, int64_t M, int64_t N, uint64_t seed, uint64_t stream,
+                    int zkind, int32_t* r, double* W_out, double* u_out)
+{
+    return resample_impl(w, 0, M, N, seed, stream, zkind, r, W_out, u_out);
+}
+
 int dcro_resample_f32(const float* w, int64_t M, int64_t N, uint64_t seed, uint64_t stream,
                       int zkind, int32_t* r, double* W_out, double* u_out)
 {

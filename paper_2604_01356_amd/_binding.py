@@ -75,6 +75,9 @@ def library():
     lib.dcr_resample_scheme.argtypes = [P, i64, i64, u64, u64, ctypes.c_int, ctypes.c_int, P, P,
                                         P, P, P, sz, P]
     lib.dcr_resample_scheme.restype = ctypes.c_int
+    lib.dcr_resample_outer.argtypes = [P, i64, P, i64, i64, u64, u64, ctypes.c_int, ctypes.c_int,
+                                       P, P, P, P, P, sz, P]
+    lib.dcr_resample_outer.restype = ctypes.c_int
     lib.dcr_scheme_uniforms.argtypes = [i64, u64, u64, ctypes.c_int, P, P]
     lib.dcr_scheme_uniforms.restype = ctypes.c_int
     lib.dcr_profile_begin.argtypes = [i32]
@@ -221,6 +224,33 @@ def dcr_resample_scheme(w, N: int, seed: int, stream_id: int = 0, scheme: int = 
     _check("dcr_resample_scheme", library().dcr_resample_scheme(
         _ptr(w), M, N, int(seed), int(stream_id), p, int(scheme), _ptr(r), _ptr(W_out),
         _ptr(u_out), _ptr(dev_status), _ptr(ws), ws.numel(), _stream(w.device)))
+    return r[:N]
+
+
+def dcr_resample_outer(a, b, N: int, seed: int, stream_id: int = 0,
+                       scheme: int = DCR_MULTINOMIAL, r=None, W_out=None, u_out=None,
+                       dev_status=None, ws=None):
+    """End to end on the weights w[i*P + k] = a[i] * b[k] (a, b both float64 or
+    both float32), formed on the fly."""
+    import torch
+    _dev_tensor(a, "a")
+    _dev_tensor(b, "b")
+    if a.dtype != b.dtype:
+        raise TypeError("a and b must have the same dtype")
+    p = precision_of(a)
+    Na, P = a.numel(), b.numel()
+    M = Na * P
+    N = int(N)
+    if r is None:
+        r = torch.empty(max(N, 1), dtype=torch.int32, device=a.device)
+    _dev_tensor(r, "r", torch.int32, N)
+    _dev_tensor(W_out, "W_out", torch.float64, M)
+    _dev_tensor(u_out, "u_out", torch.float64, N)
+    _dev_tensor(dev_status, "dev_status", torch.int32, 1)
+    ws = _workspace(ws, M, N, p, a.device)
+    _check("dcr_resample_outer", library().dcr_resample_outer(
+        _ptr(a), Na, _ptr(b), P, N, int(seed), int(stream_id), p, int(scheme), _ptr(r),
+        _ptr(W_out), _ptr(u_out), _ptr(dev_status), _ptr(ws), ws.numel(), _stream(a.device)))
     return r[:N]
 
 

@@ -242,6 +242,14 @@ bool cache_lookup(const char* path, int64_t B, int64_t sumM, int64_t sumN, int p
 
 }  // namespace
 
+namespace {
+dcr_status resample_from(const dcr::WSource& src, int64_t M, int64_t N, uint64_t seed,
+                         uint64_t stream_id, dcr_precision p, dcr_scheme scheme, int32_t* r,
+                         double* W_opt, double* u_opt, int32_t* dev_status, void* ws,
+                         size_t ws_bytes, hipStream_t stream);
+bool valid_scheme(dcr_scheme s);
+}  // namespace
+
 extern "C" {
 
 const char* dcr_status_string(dcr_status s) {
@@ -278,13 +286,15 @@ dcr_status dcr_cumulative_weights(const void* w, int64_t M, dcr_precision p, dou
     const SharedArgs sh = shared_args(L, ws);
     const int prec = prec_code(p);
     const int vec = (aligned16(w) ? 1 : 0) | (aligned16(W) ? 2 : 0);
-    hipError_t e = timed(kKReduce, stream, [&] { return dcr::launch_reduce(prec, w, wa, za, vec, stream); });
+    dcr::WSource src;
+    src.w = w;
+    hipError_t e = timed(kKReduce, stream, [&] { return dcr::launch_reduce(prec, src, wa, za, vec, stream); });
     if (e == hipSuccess)
         e = timed(kKCarries, stream,
                   [&] { return dcr::launch_carries(wa, za, sh, dev_status, total, stream); });
     if (e == hipSuccess)
         e = timed(kKMatW, stream,
-                  [&] { return dcr::launch_materialize_w(prec, w, wa, sh, W, vec, stream); });
+                  [&] { return dcr::launch_materialize_w(prec, src, wa, sh, W, vec, stream); });
     return hip_status(e);
 }
 
@@ -301,7 +311,7 @@ dcr_status dcr_sorted_uniforms(int64_t N, uint64_t seed, uint64_t stream_id, dcr
     const SharedArgs sh = shared_args(L, ws);
     const int prec = prec_code(p);
     hipError_t e = timed(kKReduce, stream,
-                         [&] { return dcr::launch_reduce(prec, nullptr, wa, za, 0, stream); });
+                         [&] { return dcr::launch_reduce(prec, dcr::WSource{}, wa, za, 0, stream); });
     if (e == hipSuccess)
         e = timed(kKCarries, stream,
                   [&] { return dcr::launch_carries(wa, za, sh, nullptr, nullptr, stream); });
@@ -322,9 +332,15 @@ dcr_status dcr_inverse_cmf(const double* W, int64_t M, const double* u, int64_t 
     return hip_status(e);
 }
 
-static bool valid_scheme(dcr_scheme s) {
+}  // extern "C"
+
+namespace {
+bool valid_scheme(dcr_scheme s) {
     return s == DCR_MULTINOMIAL || s == DCR_STRATIFIED || s == DCR_SYSTEMATIC;
 }
+}  // namespace
+
+extern "C" {
 
 dcr_status dcr_scheme_uniforms(int64_t N, uint64_t seed, uint64_t stream_id, dcr_scheme scheme,
                                double* u, hipStream_t stream) {
@@ -351,7 +367,36 @@ dcr_status dcr_resample_scheme(const void* w, int64_t M, int64_t N, uint64_t see
                                uint64_t stream_id, dcr_precision p, dcr_scheme scheme, int32_t* r,
                                double* W_opt, double* u_opt, int32_t* dev_status, void* ws,
                                size_t ws_bytes, hipStream_t stream) {
-    if (M < 1 || M > kMaxM || N < 0 || N > kMaxN || !w || !ws) return DCR_ERR_INVALID_ARGUMENT;
+    if (!w) return DCR_ERR_INVALID_ARGUMENT;
+    dcr::WSource src;
+    src.w = w;
+    return resample_from(src, M, N, seed, stream_id, p, scheme, r, W_opt, u_opt, dev_status, ws,
+                         ws_bytes, stream);
+}
+
+dcr_status dcr_resample_outer(const void* a, int64_t Na, const void* b, int64_t P, int64_t N,
+                              uint64_t seed, uint64_t stream_id, dcr_precision p,
+                              dcr_scheme scheme, int32_t* r, double* W_opt, double* u_opt,
+                              int32_t* dev_status, void* ws, size_t ws_bytes,
+                              hipStream_t stream) {
+    if (!a || !b || Na < 1 || P < 1 || Na > kMaxM / P) return DCR_ERR_INVALID_ARGUMENT;
+    dcr::WSource src;
+    src.a = a;
+    src.b = b;
+    src.P = P;
+    return resample_from(src, Na * P, N, seed, stream_id, p, scheme, r, W_opt, u_opt, dev_status,
+                         ws, ws_bytes, stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+dcr_status resample_from(const dcr::WSource& src, int64_t M, int64_t N, uint64_t seed,
+                         uint64_t stream_id, dcr_precision p, dcr_scheme scheme, int32_t* r,
+                         double* W_opt, double* u_opt, int32_t* dev_status, void* ws,
+                         size_t ws_bytes, hipStream_t stream) {
+    if (M < 1 || M > kMaxM || N < 0 || N > kMaxN || !ws) return DCR_ERR_INVALID_ARGUMENT;
     if (N > 0 && !r) return DCR_ERR_INVALID_ARGUMENT;
     if (!valid_prec(p) || !valid_scheme(scheme)) return DCR_ERR_UNSUPPORTED;
     if ((reinterpret_cast<uintptr_t>(ws) & 255u) != 0) return DCR_ERR_INVALID_ARGUMENT;
@@ -361,19 +406,20 @@ dcr_status dcr_resample_scheme(const void* w, int64_t M, int64_t N, uint64_t see
     const ZArgs za = z_args(L, ws, N, seed, stream_id, scheme);
     const SharedArgs sh = shared_args(L, ws);
     const int prec = prec_code(p);
-    const int vec = (aligned16(w) ? 1 : 0) | (aligned16(W_opt) ? 2 : 0);
+    // an outer product has no alignment to honour
+    const int vec = ((src.outer() || aligned16(src.w)) ? 1 : 0) | (aligned16(W_opt) ? 2 : 0);
     int32_t* wide = at<int32_t>(ws, L.wide);
     hipError_t e = timed(kKReduce, stream,
-                         [&] { return dcr::launch_reduce(prec, w, wa, za, vec, stream); });
+                         [&] { return dcr::launch_reduce(prec, src, wa, za, vec, stream); });
     if (dcr::finish_fits(wa, za)) {
         // block scans, uniforms and map in one launch
         if (e == hipSuccess)
             e = timed(kKFinish, stream, [&] {
-                return dcr::launch_finish(prec, w, wa, za, sh, dev_status, u_opt, r, vec, stream);
+                return dcr::launch_finish(prec, src, wa, za, sh, dev_status, u_opt, r, vec, stream);
             });
         if (e == hipSuccess && W_opt)
             e = timed(kKMatW, stream,
-                      [&] { return dcr::launch_materialize_w(prec, w, wa, sh, W_opt, vec, stream); });
+                      [&] { return dcr::launch_materialize_w(prec, src, wa, sh, W_opt, vec, stream); });
         return hip_status(e);
     }
     if (e == hipSuccess)
@@ -381,23 +427,27 @@ dcr_status dcr_resample_scheme(const void* w, int64_t M, int64_t N, uint64_t see
                   [&] { return dcr::launch_carries(wa, za, sh, dev_status, nullptr, stream); });
     if (e == hipSuccess && W_opt)
         e = timed(kKMatW, stream,
-                  [&] { return dcr::launch_materialize_w(prec, w, wa, sh, W_opt, vec, stream); });
+                  [&] { return dcr::launch_materialize_w(prec, src, wa, sh, W_opt, vec, stream); });
     if (e == hipSuccess && N > 0) {
         if (dcr::map_is_dense(M, N)) {
             e = timed(kKMapDense, stream, [&] {
-                return dcr::launch_map_dense(prec, w, wa, za, sh, u_opt, r, wide, stream);
+                return dcr::launch_map_dense(prec, src, wa, za, sh, u_opt, r, wide, stream);
             });
             if (e == hipSuccess)
                 e = timed(kKMapWide, stream, [&] {
-                    return dcr::launch_map_wide(prec, w, wa, za, sh, r, wide, vec, stream);
+                    return dcr::launch_map_wide(prec, src, wa, za, sh, r, wide, vec, stream);
                 });
         } else
             e = timed(kKMapFused, stream, [&] {
-                return dcr::launch_map_fused(prec, w, wa, za, sh, u_opt, r, vec, stream);
+                return dcr::launch_map_fused(prec, src, wa, za, sh, u_opt, r, vec, stream);
             });
     }
     return hip_status(e);
 }
+
+}  // namespace
+
+extern "C" {
 
 
 dcr_status dcr_batched_workspace_bytes(int32_t B, int64_t sumM_max, int64_t sumN_max,

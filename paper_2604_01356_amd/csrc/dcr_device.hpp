@@ -205,6 +205,78 @@ __device__ __forceinline__ RawChunk<Tin> load_raw_n(const Tin* __restrict__ p, i
     return rc;
 }
 
+// ---------------------------------------------------------------------------
+// Weight sources.  The kernels read weights either from an array (`const T*`)
+// or from an outer product, w_j = a[j / P] * b[j % P] (the weights of an
+// ensemble Gaussian mixture step: particle i, likelihood component k), formed
+// in binary64 (exact for binary32 factors), so that the M weights are never
+// read from memory.  src_* (source, element offset, count) return a chunk.
+// ---------------------------------------------------------------------------
+template <typename W>
+struct SrcElem;
+template <typename T>
+struct SrcElem<const T*> {
+    using type = T;
+};
+template <typename T>
+struct SrcElem<Outer<T>> {
+    using type = double;
+};
+
+template <typename T>
+__device__ __forceinline__ RawChunk<T> src_raw(const T* __restrict__ w, int64_t j) {
+    return load_raw<T>(w + j);
+}
+template <typename T>
+__device__ __forceinline__ RawChunk<T> src_raw_any(const T* __restrict__ w, int64_t j) {
+    return load_raw_any<T>(w + j);
+}
+template <typename T>
+__device__ __forceinline__ RawChunk<T> src_raw_n(const T* __restrict__ w, int64_t j, int n) {
+    return load_raw_n<T>(w + (n > 0 ? j : 0), n);
+}
+template <typename T>
+__device__ __forceinline__ void src_chunk(const T* __restrict__ w, int64_t j, int n, bool vec_ok,
+                                          double (&x)[kLane]) {
+    load_chunk<T>(w + (n > 0 ? j : 0), n, vec_ok, x);
+}
+
+// Outer product: the first product's factors by one division, then walk k.
+template <typename T>
+__device__ __forceinline__ RawChunk<double> src_raw_n(const Outer<T>& o, int64_t j, int n) {
+    RawChunk<double> rc;
+    int64_t i = (n > 0) ? j / o.P : 0;
+    int64_t k = (n > 0) ? j - i * o.P : 0;
+#pragma unroll
+    for (int q = 0; q < kLane; ++q) {
+        double x = 0.0;
+        if (q < n) {
+            x = static_cast<double>(o.a[i]) * static_cast<double>(o.b[k]);
+            if (++k == o.P) {
+                k = 0;
+                ++i;
+            }
+        }
+        rc.v[q / 2][q % 2] = x;
+    }
+    return rc;
+}
+template <typename T>
+__device__ __forceinline__ RawChunk<double> src_raw(const Outer<T>& o, int64_t j) {
+    return src_raw_n(o, j, kLane);
+}
+template <typename T>
+__device__ __forceinline__ RawChunk<double> src_raw_any(const Outer<T>& o, int64_t j) {
+    return src_raw_n(o, j, kLane);
+}
+template <typename T>
+__device__ __forceinline__ void src_chunk(const Outer<T>& o, int64_t j, int n, bool,
+                                          double (&x)[kLane]) {
+    const RawChunk<double> rc = src_raw_n(o, j, n);
+#pragma unroll
+    for (int q = 0; q < kLane; ++q) x[q] = rc.at(q);
+}
+
 // Left-to-right binary64 sum of a raw chunk; also folds its elements into a
 // running minimum (in the input precision) used to detect negative weights.
 template <typename Tin>

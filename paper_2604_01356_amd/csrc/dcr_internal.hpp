@@ -15,6 +15,15 @@ constexpr int kPrecFP32 = 1;
 constexpr int kStatusOk = 0;
 constexpr int kStatusBadWeights = 6;
 
+// Weights given as an outer product: w_j = a[j / P] * b[j % P] (binary64
+// product of the two factors, exact for binary32 factors).
+template <typename T>
+struct Outer {
+    const T* a;
+    const T* b;
+    int64_t P;
+};
+
 // Weight side: M weights in nb blocks of 32768.
 struct WArgs {
     int64_t M;

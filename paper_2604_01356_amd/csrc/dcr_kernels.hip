@@ -126,15 +126,62 @@ __device__ __forceinline__ void reduce_z_block(const ZArgs& za, int64_t g, doubl
 // sub-tile ends and the block total (NaN for an inadmissible block).  The
 // three LDS buffers stream binary32 weights; sb0 is also the epilogue's
 // scratch.  All threads call it.
+// The end of a weight block, whatever its load path: the lane-chunk totals
+// lt (round it = sub-tile 16 it + row) become the sub-tile totals, the stored
+// sub-tile ends and the block total.  sb0 is at least ReduceSmem<>::kEpi bytes.
+__device__ __forceinline__ void reduce_w_epilogue(const double (&lt)[kWIters], int bad,
+                                                  const WArgs& wa, int64_t b, unsigned char* sb0) {
+    double* lane_tot = reinterpret_cast<double*>(sb0);   // [kWIters][kThreads]
+    double* sub_tot = lane_tot + kWIters * kThreads;      // [kWSubPerBlock]
+    double* sub_end = sub_tot + kWSubPerBlock;            // [kWSubPerBlock]
+    const int t = threadIdx.x;
+    if (wa.chunk_tot) {
+        // lane chunk (sub-tile 16 it + row, lane) of the block: coalesced per round
+        double* ct = wa.chunk_tot + b * (kWSubPerBlock * kRowLanes);
+#pragma unroll
+        for (int it = 0; it < kWIters; ++it) ct[it * kThreads + t] = lt[it];
+    }
+    lds_barrier();   // the first stream buffer becomes the epilogue's scratch
+#pragma unroll
+    for (int it = 0; it < kWIters; ++it) lane_tot[it * kThreads + t] = lt[it];
+    bad = block_any(bad);
+    if (t < kWSubPerBlock) {
+        const int it = t / kRows;
+        const int r = t % kRows;
+        const double* p = lane_tot + it * kThreads + r * kRowLanes;
+        double lv[kRowLanes];
+#pragma unroll
+        for (int l = 0; l < kRowLanes; ++l) lv[l] = p[l];
+        double c = lv[0];
+#pragma unroll
+        for (int l = 1; l < kRowLanes; ++l) c = c + lv[l];
+        sub_tot[t] = c;
+    }
+    lds_barrier();
+    if (t == 0) {
+        double s = 0.0;
+#pragma unroll 16
+        for (int q = 0; q < kWSubPerBlock; ++q) {
+            s = s + sub_tot[q];
+            sub_end[q] = s;
+        }
+    }
+    lds_barrier();
+    if (t < kWSubPerBlock) wa.sub_end[b * kWSubPerBlock + t] = sub_end[t];
+    if (t == 0) {
+        // an inadmissible block (negative weight, NaN, infinity or overflow)
+        // publishes a NaN total, which every scan of the totals detects
+        const double tot = sub_end[kWSubPerBlock - 1];
+        wa.blk_tot[b] = (bad || !(tot < __builtin_huge_val())) ? __builtin_nan("") : tot;
+    }
+}
+
 template <typename Tin, int DEPTH = kStreamDepth>
 __device__ __forceinline__ void reduce_w_block(const Tin* __restrict__ w, const WArgs& wa, int64_t b,
                                                int vec_ok, unsigned char* sb0, unsigned char* sb1,
                                                unsigned char* sb2) {
     static_assert(DEPTH == 1 || DEPTH == 2, "one or two rounds in flight");
     constexpr int kBufs = DEPTH + 1;
-    double* lane_tot = reinterpret_cast<double*>(sb0);   // [kWIters][kThreads]
-    double* sub_tot = lane_tot + kWIters * kThreads;      // [kWSubPerBlock]
-    double* sub_end = sub_tot + kWSubPerBlock;            // [kWSubPerBlock]
     const int t = threadIdx.x;
     const int row = t / kRowLanes;
     const int lane = t % kRowLanes;
@@ -225,45 +272,41 @@ __device__ __forceinline__ void reduce_w_block(const Tin* __restrict__ w, const 
         }
         bad = (mn < static_cast<Tin>(0)) ? 1 : 0;
     }
-    if (wa.chunk_tot) {
-        // lane chunk (sub-tile 16 it + row, lane) of the block: coalesced per round
-        double* ct = wa.chunk_tot + b * (kWSubPerBlock * kRowLanes);
+    reduce_w_epilogue(lt, bad, wa, b, sb0);
+}
+
+// Weight block b of an outer-product source: each lane forms its chunks'
+// products (nothing of length M is read), then the common epilogue.
+template <typename T>
+__device__ __forceinline__ void reduce_w_block_outer(const Outer<T>& o, const WArgs& wa, int64_t b,
+                                                     unsigned char* sb0) {
+    const int t = threadIdx.x;
+    const int row = t / kRowLanes;
+    const int lane = t % kRowLanes;
+    const int64_t j00 = b * kWBlock + row * kSub + lane * kLane;
+    double lt[kWIters];
+    double mn = 0.0;
+#pragma unroll 2
+    for (int it = 0; it < kWIters; ++it) {
+        const int64_t j0 = j00 + static_cast<int64_t>(it) * kRows * kSub;
+        const RawChunk<double> rc = src_raw_n(o, j0, clamp_count(wa.M - j0, kLane));
+        const double ct = raw_sum<double>(rc, mn);
 #pragma unroll
-        for (int it = 0; it < kWIters; ++it) ct[it * kThreads + t] = lt[it];
+        for (int q = 0; q < kWIters; ++q)
+            if (q == it) lt[q] = ct;
     }
-    lds_barrier();   // the first stream buffer becomes the epilogue's scratch
-#pragma unroll
-    for (int it = 0; it < kWIters; ++it) lane_tot[it * kThreads + t] = lt[it];
-    bad = block_any(bad);
-    if (t < kWSubPerBlock) {
-        const int it = t / kRows;
-        const int r = t % kRows;
-        const double* p = lane_tot + it * kThreads + r * kRowLanes;
-        double lv[kRowLanes];
-#pragma unroll
-        for (int l = 0; l < kRowLanes; ++l) lv[l] = p[l];
-        double c = lv[0];
-#pragma unroll
-        for (int l = 1; l < kRowLanes; ++l) c = c + lv[l];
-        sub_tot[t] = c;
+    reduce_w_epilogue(lt, (mn < 0.0) ? 1 : 0, wa, b, sb0);
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(kThreads) void k_reduce_outer(Outer<T> o, WArgs wa, ZArgs za) {
+    __shared__ __attribute__((aligned(16))) unsigned char sb0[ReduceSmem<double>::kBuf0];
+    if (static_cast<int64_t>(blockIdx.x) < za.nb) {
+        double* lane_tot = reinterpret_cast<double*>(sb0);
+        reduce_z_block<P>(za, blockIdx.x, lane_tot, lane_tot + kThreads);
+        return;
     }
-    lds_barrier();
-    if (t == 0) {
-        double s = 0.0;
-#pragma unroll 16
-        for (int q = 0; q < kWSubPerBlock; ++q) {
-            s = s + sub_tot[q];
-            sub_end[q] = s;
-        }
-    }
-    lds_barrier();
-    if (t < kWSubPerBlock) wa.sub_end[b * kWSubPerBlock + t] = sub_end[t];
-    if (t == 0) {
-        // an inadmissible block (negative weight, NaN, infinity or overflow)
-        // publishes a NaN total, which every scan of the totals detects
-        const double tot = sub_end[kWSubPerBlock - 1];
-        wa.blk_tot[b] = (bad || !(tot < __builtin_huge_val())) ? __builtin_nan("") : tot;
-    }
+    reduce_w_block_outer<T>(o, wa, static_cast<int64_t>(blockIdx.x) - za.nb, sb0);
 }
 
 template <typename Tin, int P>
@@ -519,10 +562,8 @@ __global__ __launch_bounds__(kScanThreads) void k_carries(WArgs wa, ZArgs za, Sh
 // ---------------------------------------------------------------------------
 // k_materialize_w: one workgroup per (weight block, round of 16 sub-tiles).
 // ---------------------------------------------------------------------------
-template <typename Tin>
-__global__ __launch_bounds__(kThreads) void k_materialize_w(const Tin* __restrict__ w, WArgs wa,
-                                                            SharedArgs sh, double* __restrict__ W,
-                                                            int vec_ok) {
+template <typename Src>
+__device__ __forceinline__ void k_materialize_w_body(Src w, WArgs wa, SharedArgs sh, double* __restrict__ W, int vec_ok) {
     __shared__ double lane_tot[kThreads];
     const int t = threadIdx.x;
     const int row = t / kRowLanes;
@@ -534,7 +575,7 @@ __global__ __launch_bounds__(kThreads) void k_materialize_w(const Tin* __restric
     const int64_t j0 = blk0 + static_cast<int64_t>(s) * kSub + lane * kLane;
     const int nv = clamp_count(wa.M - j0, kLane);
     double x[kLane];
-    load_chunk<Tin>(w + (nv > 0 ? j0 : 0), nv, (vec_ok & 1) != 0, x);
+    src_chunk(w, j0, nv, (vec_ok & 1) != 0, x);
     double p[kLane];
     p[0] = x[0];
 #pragma unroll
@@ -567,6 +608,16 @@ __global__ __launch_bounds__(kThreads) void k_materialize_w(const Tin* __restric
     } else {
         for (int k = 0; k < nv; ++k) W[j0 + k] = out[k];
     }
+}
+
+template <typename Tin>
+__global__ __launch_bounds__(kThreads) void k_materialize_w(const Tin* __restrict__ w, WArgs wa, SharedArgs sh, double* __restrict__ W, int vec_ok) {
+    k_materialize_w_body<const Tin*>(w, wa, sh, W, vec_ok);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_materialize_w_outer(Outer<T> w, WArgs wa, SharedArgs sh, double* __restrict__ W, int vec_ok) {
+    k_materialize_w_body<Outer<T>>(w, wa, sh, W, vec_ok);
 }
 
 // ---------------------------------------------------------------------------
@@ -735,10 +786,10 @@ __device__ int64_t locate_subtile_index(const WArgs& wa, const double* sbeta, in
     return b * kWSubPerBlock + quad_sum(cnt);
 }
 
-template <typename Tin>
-__device__ void map_quad(const Tin* __restrict__ w, const WArgs& wa, const double* sbeta,
-                         int64_t kstride, int ns, double x, int64_t i, int qi,
-                         int32_t* __restrict__ r, int vec_ok) {
+template <typename Src>
+__device__ void map_quad(Src w, const WArgs& wa, const double* sbeta, int64_t kstride, int ns,
+                         double x, int64_t i, int qi, int32_t* __restrict__ r, int vec_ok) {
+    using Elem = typename SrcElem<Src>::type;
     const SubtileLoc loc = locate_subtile(wa, sbeta, kstride, ns, x, qi);
     const int64_t blk0 = loc.blk0, jlast = loc.jlast;
     const int s = loc.s, nsub = loc.nsub;
@@ -750,15 +801,15 @@ __device__ void map_quad(const Tin* __restrict__ w, const WArgs& wa, const doubl
     constexpr int kChunks = kRowLanes / kQuad;
     double tl[kChunks];
     const bool full_sub = (slen == kSub) && (vec_ok & 1);
-    RawChunk<Tin> rc[kChunks];
+    RawChunk<Elem> rc[kChunks];
     if (full_sub) {
 #pragma unroll
         for (int q = 0; q < kChunks; ++q)
-            rc[q] = load_raw<Tin>(w + sub0 + (kChunks * qi + q) * kLane);
+            rc[q] = src_raw(w, sub0 + (kChunks * qi + q) * kLane);
 #pragma unroll
         for (int q = 0; q < kChunks; ++q) {
-            Tin mn = static_cast<Tin>(0);
-            tl[q] = raw_sum<Tin>(rc[q], mn);
+            Elem mn = static_cast<Elem>(0);
+            tl[q] = raw_sum<Elem>(rc[q], mn);
         }
     } else {
 #pragma unroll
@@ -766,7 +817,7 @@ __device__ void map_quad(const Tin* __restrict__ w, const WArgs& wa, const doubl
             const int l = kChunks * qi + q;
             const int nv = (l < nl) ? ((slen - l * kLane < kLane) ? slen - l * kLane : kLane) : 0;
             double xx[kLane];
-            load_chunk<Tin>(w + (nv > 0 ? sub0 + l * kLane : 0), nv, (vec_ok & 1) != 0, xx);
+            src_chunk(w, sub0 + l * kLane, nv, (vec_ok & 1) != 0, xx);
             tl[q] = chunk_sum(xx);
         }
     }
@@ -807,14 +858,14 @@ __device__ void map_quad(const Tin* __restrict__ w, const WArgs& wa, const doubl
     const int nv = (slen - lf * kLane < kLane) ? slen - lf * kLane : kLane;
     double xx[kLane];
     if (full_sub) {   // the chunk is still in registers
-        RawChunk<Tin> sel = rc[0];
+        RawChunk<Elem> sel = rc[0];
 #pragma unroll
         for (int q = 1; q < kChunks; ++q)
             if (q == lf % kChunks) sel = rc[q];
 #pragma unroll
         for (int k = 0; k < kLane; ++k) xx[k] = sel.at(k);
     } else {
-        load_chunk<Tin>(w + l0, nv, (vec_ok & 1) != 0, xx);
+        src_chunk(w, l0, nv, (vec_ok & 1) != 0, xx);
     }
     double pk = 0.0;
     int64_t jr = l0 + nv - 1;
@@ -832,8 +883,8 @@ __device__ void map_quad(const Tin* __restrict__ w, const WArgs& wa, const doubl
 
 // Map of draws 64c .. 64c+63 with the scanned block ends read from memory
 // (after k_carries).  All threads call it; sbeta is kBetaLds doubles of LDS.
-template <typename Tin>
-__device__ __forceinline__ void map_chunk(const Tin* __restrict__ w, const WArgs& wa, const ZArgs& za,
+template <typename Src>
+__device__ __forceinline__ void map_chunk(Src w, const WArgs& wa, const ZArgs& za,
                                           const SharedArgs& sh, double* __restrict__ u_out,
                                           int32_t* __restrict__ r, int vec_ok, int64_t c,
                                           double* sbeta) {
@@ -860,7 +911,7 @@ __device__ __forceinline__ void map_chunk(const Tin* __restrict__ w, const WArgs
         if ((t & (kQuad - 1)) == 0) r[i] = -1;
         return;
     }
-    map_quad<Tin>(w, wa, sbeta, kstride, ns, x, i, t & (kQuad - 1), r, vec_ok);
+    map_quad<Src>(w, wa, sbeta, kstride, ns, x, i, t & (kQuad - 1), r, vec_ok);
 }
 
 template <typename Tin>
@@ -868,7 +919,15 @@ __global__ __launch_bounds__(kThreads) void k_map_fused(const Tin* __restrict__ 
                                                         SharedArgs sh, double* __restrict__ u_out,
                                                         int32_t* __restrict__ r, int vec_ok) {
     __shared__ double sbeta[kBetaLds];
-    map_chunk<Tin>(w, wa, za, sh, u_out, r, vec_ok, blockIdx.x, sbeta);
+    map_chunk<const Tin*>(w, wa, za, sh, u_out, r, vec_ok, blockIdx.x, sbeta);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_map_fused_outer(Outer<T> w, WArgs wa, ZArgs za,
+                                                              SharedArgs sh, double* __restrict__ u_out,
+                                                              int32_t* __restrict__ r) {
+    __shared__ double sbeta[kBetaLds];
+    map_chunk<Outer<T>>(w, wa, za, sh, u_out, r, 1, blockIdx.x, sbeta);
 }
 
 // ---------------------------------------------------------------------------
@@ -893,11 +952,9 @@ constexpr int kWinLen = kWinSub * kSub;       // weights per window (= kThreads 
 constexpr int kMaxWin = 4;
 static_assert(kWinLen <= kBetaLds, "the window reuses the block-end stage");
 
-template <typename Tin>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_map_dense(const Tin* __restrict__ w, WArgs wa, ZArgs za,
-                                                        SharedArgs sh, double* __restrict__ u_out,
-                                                        int32_t* __restrict__ r,
-                                                        int32_t* __restrict__ wide, int per_wg) {
+template <typename Src>
+__device__ __forceinline__ void k_map_dense_body(Src w, WArgs wa, ZArgs za, SharedArgs sh, double* __restrict__ u_out, int32_t* __restrict__ r, int32_t* __restrict__ wide, int per_wg) {
+    using Elem = typename SrcElem<Src>::type;
     // block ends for the search of the span, then a window of normalised
     // cumulative weights
     __shared__ double lds[kBetaLds];
@@ -993,7 +1050,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
             beta_b = (b == 0) ? 0.0 : wa.beta[b - 1];
             beta_n = wa.beta[b];
         }
-        const RawChunk<Tin> rc = load_raw_n<Tin>(w + (nv > 0 ? j0 : 0), nv);
+        const RawChunk<Elem> rc = src_raw_n(w, j0, nv);
         {
             double pt = rc.at(0);
 #pragma unroll
@@ -1067,12 +1124,19 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     }
 }
 
-// The flagged (wide-span) chunks of k_map_dense: one quad search per uniform.
 template <typename Tin>
-__global__ __launch_bounds__(kThreads) void k_map_wide(const Tin* __restrict__ w, WArgs wa, ZArgs za,
-                                                       SharedArgs sh, int32_t* __restrict__ r,
-                                                       const int32_t* __restrict__ wide,
-                                                       int vec_ok, int per_wg) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_map_dense(const Tin* __restrict__ w, WArgs wa, ZArgs za, SharedArgs sh, double* __restrict__ u_out, int32_t* __restrict__ r, int32_t* __restrict__ wide, int per_wg) {
+    k_map_dense_body<const Tin*>(w, wa, za, sh, u_out, r, wide, per_wg);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_map_dense_outer(Outer<T> w, WArgs wa, ZArgs za, SharedArgs sh, double* __restrict__ u_out, int32_t* __restrict__ r, int32_t* __restrict__ wide, int per_wg) {
+    k_map_dense_body<Outer<T>>(w, wa, za, sh, u_out, r, wide, per_wg);
+}
+
+// The flagged (wide-span) chunks of k_map_dense: one quad search per uniform.
+template <typename Src>
+__device__ __forceinline__ void k_map_wide_body(Src w, WArgs wa, ZArgs za, SharedArgs sh, int32_t* __restrict__ r, const int32_t* __restrict__ wide, int vec_ok, int per_wg) {
     __shared__ double sbeta[kBetaLds];
     if (wide[blockIdx.x] == 0) return;   // workgroup-uniform
     const int t = threadIdx.x;
@@ -1090,8 +1154,18 @@ __global__ __launch_bounds__(kThreads) void k_map_wide(const Tin* __restrict__ w
     const int64_t c1 = (c0 + per_wg < za.N) ? c0 + per_wg : za.N;
     for (int64_t i = c0 + t / kQuad; i < c1; i += kUPerWG) {
         const double x = threshold_for(uniform_at(za, ztot, i), total);
-        map_quad<Tin>(w, wa, sbeta, kstride, ns, x, i, t & (kQuad - 1), r, vec_ok);
+        map_quad<Src>(w, wa, sbeta, kstride, ns, x, i, t & (kQuad - 1), r, vec_ok);
     }
+}
+
+template <typename Tin>
+__global__ __launch_bounds__(kThreads) void k_map_wide(const Tin* __restrict__ w, WArgs wa, ZArgs za, SharedArgs sh, int32_t* __restrict__ r, const int32_t* __restrict__ wide, int vec_ok, int per_wg) {
+    k_map_wide_body<const Tin*>(w, wa, za, sh, r, wide, vec_ok, per_wg);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_map_wide_outer(Outer<T> w, WArgs wa, ZArgs za, SharedArgs sh, int32_t* __restrict__ r, const int32_t* __restrict__ wide, int vec_ok, int per_wg) {
+    k_map_wide_body<Outer<T>>(w, wa, za, sh, r, wide, vec_ok, per_wg);
 }
 
 // ---------------------------------------------------------------------------
@@ -1100,11 +1174,8 @@ __global__ __launch_bounds__(kThreads) void k_map_wide(const Tin* __restrict__ w
 // (the same scan as k_carries, so the same bits), forms the uniforms of its 64
 // draws and maps them; workgroup 0 also publishes the scans, totals and status.
 // ---------------------------------------------------------------------------
-template <typename Tin>
-__global__ __launch_bounds__(kThreads) void k_finish(const Tin* __restrict__ w, WArgs wa, ZArgs za,
-                                                     SharedArgs sh, int32_t* dev_status,
-                                                     double* __restrict__ u_out,
-                                                     int32_t* __restrict__ r, int vec_ok) {
+template <typename Src>
+__device__ __forceinline__ void k_finish_body(Src w, WArgs wa, ZArgs za, SharedArgs sh, int32_t* dev_status, double* __restrict__ u_out, int32_t* __restrict__ r, int vec_ok) {
     __shared__ double sbeta[kBetaLds];
     __shared__ double szbeta[kFinishMaxZBlocks];
     __shared__ ScanLds L;
@@ -1144,7 +1215,17 @@ __global__ __launch_bounds__(kThreads) void k_finish(const Tin* __restrict__ w, 
         return;
     }
     const double x = threshold_for(uu, tot);
-    map_quad<Tin>(w, wa, sbeta, 1, static_cast<int>(wa.nb), x, i, qi, r, vec_ok);
+    map_quad<Src>(w, wa, sbeta, 1, static_cast<int>(wa.nb), x, i, qi, r, vec_ok);
+}
+
+template <typename Tin>
+__global__ __launch_bounds__(kThreads) void k_finish(const Tin* __restrict__ w, WArgs wa, ZArgs za, SharedArgs sh, int32_t* dev_status, double* __restrict__ u_out, int32_t* __restrict__ r, int vec_ok) {
+    k_finish_body<const Tin*>(w, wa, za, sh, dev_status, u_out, r, vec_ok);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_finish_outer(Outer<T> w, WArgs wa, ZArgs za, SharedArgs sh, int32_t* dev_status, double* __restrict__ u_out, int32_t* __restrict__ r, int vec_ok) {
+    k_finish_body<Outer<T>>(w, wa, za, sh, dev_status, u_out, r, vec_ok);
 }
 
 // ---------------------------------------------------------------------------
@@ -1715,10 +1796,21 @@ static hipError_t launch_reduce_t(const void* w, const WArgs& wa, const ZArgs& z
     return hipGetLastError();
 }
 
-hipError_t launch_reduce(int prec, const void* w, const WArgs& wa, const ZArgs& za, int vec_ok,
+hipError_t launch_reduce(int prec, const WSource& src, const WArgs& wa, const ZArgs& za, int vec_ok,
                          hipStream_t s) {
-    if (prec == kPrecFP32) return launch_reduce_t<float, kPrecFP32>(w, wa, za, vec_ok, s);
-    return launch_reduce_t<double, kPrecFP64>(w, wa, za, vec_ok, s);
+    if (src.outer()) {
+        const int64_t grid = wa.nb + za.nb;
+        if (grid <= 0) return hipSuccess;
+        if (prec == kPrecFP32)
+            launch(k_reduce_outer<float, kPrecFP32>, dim3(static_cast<unsigned>(grid)),
+                   dim3(kThreads), 0, s, src.outer_as<float>(), wa, za);
+        else
+            launch(k_reduce_outer<double, kPrecFP64>, dim3(static_cast<unsigned>(grid)),
+                   dim3(kThreads), 0, s, src.outer_as<double>(), wa, za);
+        return hipGetLastError();
+    }
+    if (prec == kPrecFP32) return launch_reduce_t<float, kPrecFP32>(src.w, wa, za, vec_ok, s);
+    return launch_reduce_t<double, kPrecFP64>(src.w, wa, za, vec_ok, s);
 }
 
 hipError_t launch_carries(const WArgs& wa, const ZArgs& za, const SharedArgs& sh,
@@ -1728,11 +1820,19 @@ hipError_t launch_carries(const WArgs& wa, const ZArgs& za, const SharedArgs& sh
     return hipGetLastError();
 }
 
-hipError_t launch_materialize_w(int prec, const void* w, const WArgs& wa, const SharedArgs& sh,
+hipError_t launch_materialize_w(int prec, const WSource& src, const WArgs& wa, const SharedArgs& sh,
                                 double* W, int vec_ok, hipStream_t s) {
     const int64_t grid = wa.nb * kWIters;
     if (grid <= 0) return hipSuccess;
-    if (prec == kPrecFP32)
+    const void* w = src.w;
+    if (src.outer()) {
+        if (prec == kPrecFP32)
+            launch(k_materialize_w_outer<float>, dim3(static_cast<unsigned>(grid)), dim3(kThreads),
+                   0, s, src.outer_as<float>(), wa, sh, W, 1);
+        else
+            launch(k_materialize_w_outer<double>, dim3(static_cast<unsigned>(grid)), dim3(kThreads),
+                   0, s, src.outer_as<double>(), wa, sh, W, 1);
+    } else if (prec == kPrecFP32)
         launch(k_materialize_w<float>, dim3(static_cast<unsigned>(grid)), dim3(kThreads),
                            0, s, static_cast<const float*>(w), wa, sh, W, vec_ok);
     else
@@ -1751,12 +1851,20 @@ hipError_t launch_materialize_u(const ZArgs& za, const SharedArgs& sh, double* u
     return hipGetLastError();
 }
 
-hipError_t launch_map_fused(int prec, const void* w, const WArgs& wa, const ZArgs& za,
+hipError_t launch_map_fused(int prec, const WSource& src, const WArgs& wa, const ZArgs& za,
                             const SharedArgs& sh, double* u_out, int32_t* r, int vec_ok,
                             hipStream_t s) {
     if (za.N <= 0) return hipSuccess;
     const int64_t grid = (za.N + kUPerWG - 1) / kUPerWG;
-    if (prec == kPrecFP32)
+    const void* w = src.w;
+    if (src.outer()) {
+        if (prec == kPrecFP32)
+            launch(k_map_fused_outer<float>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0,
+                   s, src.outer_as<float>(), wa, za, sh, u_out, r);
+        else
+            launch(k_map_fused_outer<double>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0,
+                   s, src.outer_as<double>(), wa, za, sh, u_out, r);
+    } else if (prec == kPrecFP32)
         launch(k_map_fused<float>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0,
                            s, static_cast<const float*>(w), wa, za, sh, u_out, r, vec_ok);
     else
@@ -1781,13 +1889,21 @@ int64_t dense_chunks(int64_t M, int64_t N) {
     return (N + per - 1) / per;
 }
 
-hipError_t launch_map_dense(int prec, const void* w, const WArgs& wa, const ZArgs& za,
+hipError_t launch_map_dense(int prec, const WSource& src, const WArgs& wa, const ZArgs& za,
                             const SharedArgs& sh, double* u_out, int32_t* r, int32_t* wide,
                             hipStream_t s) {
     if (za.N <= 0) return hipSuccess;
     const int per = dense_per_wg(wa.M, za.N);
     const int64_t grid = dense_chunks(wa.M, za.N);
-    if (prec == kPrecFP32)
+    const void* w = src.w;
+    if (src.outer()) {
+        if (prec == kPrecFP32)
+            launch(k_map_dense_outer<float>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s,
+                   src.outer_as<float>(), wa, za, sh, u_out, r, wide, per);
+        else
+            launch(k_map_dense_outer<double>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0,
+                   s, src.outer_as<double>(), wa, za, sh, u_out, r, wide, per);
+    } else if (prec == kPrecFP32)
         launch(k_map_dense<float>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s,
                static_cast<const float*>(w), wa, za, sh, u_out, r, wide, per);
     else
@@ -1796,13 +1912,21 @@ hipError_t launch_map_dense(int prec, const void* w, const WArgs& wa, const ZArg
     return hipGetLastError();
 }
 
-hipError_t launch_map_wide(int prec, const void* w, const WArgs& wa, const ZArgs& za,
+hipError_t launch_map_wide(int prec, const WSource& src, const WArgs& wa, const ZArgs& za,
                            const SharedArgs& sh, int32_t* r, const int32_t* wide, int vec_ok,
                            hipStream_t s) {
     if (za.N <= 0) return hipSuccess;
     const int per = dense_per_wg(wa.M, za.N);
     const int64_t grid = dense_chunks(wa.M, za.N);
-    if (prec == kPrecFP32)
+    const void* w = src.w;
+    if (src.outer()) {
+        if (prec == kPrecFP32)
+            launch(k_map_wide_outer<float>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s,
+                   src.outer_as<float>(), wa, za, sh, r, wide, 1, per);
+        else
+            launch(k_map_wide_outer<double>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s,
+                   src.outer_as<double>(), wa, za, sh, r, wide, 1, per);
+    } else if (prec == kPrecFP32)
         launch(k_map_wide<float>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s,
                static_cast<const float*>(w), wa, za, sh, r, wide, vec_ok, per);
     else
@@ -1819,11 +1943,19 @@ bool finish_fits(const WArgs& wa, const ZArgs& za) {
            (za.nb >= 1 || za.scheme != kSchemeMultinomial) && za.nb <= kFinishMaxZBlocks;
 }
 
-hipError_t launch_finish(int prec, const void* w, const WArgs& wa, const ZArgs& za,
+hipError_t launch_finish(int prec, const WSource& src, const WArgs& wa, const ZArgs& za,
                          const SharedArgs& sh, int32_t* dev_status, double* u_out, int32_t* r,
                          int vec_ok, hipStream_t s) {
     const int64_t grid = (za.N + kUPerWG - 1) / kUPerWG;
-    if (prec == kPrecFP32)
+    const void* w = src.w;
+    if (src.outer()) {
+        if (prec == kPrecFP32)
+            launch(k_finish_outer<float>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s,
+                   src.outer_as<float>(), wa, za, sh, dev_status, u_out, r, 1);
+        else
+            launch(k_finish_outer<double>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s,
+                   src.outer_as<double>(), wa, za, sh, dev_status, u_out, r, 1);
+    } else if (prec == kPrecFP32)
         launch(k_finish<float>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s,
                            static_cast<const float*>(w), wa, za, sh, dev_status, u_out, r, vec_ok);
     else

@@ -19,7 +19,21 @@ struct LaunchEvents {
 };
 extern LaunchEvents g_launch_events;
 
-hipError_t launch_reduce(int prec, const void* w, const WArgs& wa, const ZArgs& za, int vec_ok,
+// Where the weights come from: an array `w` of the precision's type, or
+// (P > 0) the outer product w_j = a[j / P] * b[j % P] of two such arrays.
+struct WSource {
+    const void* w = nullptr;
+    const void* a = nullptr;
+    const void* b = nullptr;
+    int64_t P = 0;
+    bool outer() const { return P > 0; }
+    template <typename T>
+    Outer<T> outer_as() const {
+        return Outer<T>{static_cast<const T*>(a), static_cast<const T*>(b), P};
+    }
+};
+
+hipError_t launch_reduce(int prec, const WSource& src, const WArgs& wa, const ZArgs& za, int vec_ok,
                          hipStream_t s);
 bool finish_fits(const WArgs& wa, const ZArgs& za);
 
@@ -28,23 +42,23 @@ int64_t dense_chunks(int64_t M, int64_t N);   // at most ceil(N / 256)
 // k_map_dense: merges each chunk of draws and flags in `wide`
 // (dense_chunks(M, N) int32 flags) the chunks whose span is too wide to merge;
 // launch_map_wide then places the draws of the flagged chunks.
-hipError_t launch_map_dense(int prec, const void* w, const WArgs& wa, const ZArgs& za,
+hipError_t launch_map_dense(int prec, const WSource& src, const WArgs& wa, const ZArgs& za,
                             const SharedArgs& sh, double* u_out, int32_t* r, int32_t* wide,
                             hipStream_t s);
 // the flagged (wide-span) chunks left by launch_map_dense
-hipError_t launch_map_wide(int prec, const void* w, const WArgs& wa, const ZArgs& za,
+hipError_t launch_map_wide(int prec, const WSource& src, const WArgs& wa, const ZArgs& za,
                            const SharedArgs& sh, int32_t* r, const int32_t* wide, int vec_ok,
                            hipStream_t s);
 
 hipError_t launch_carries(const WArgs& wa, const ZArgs& za, const SharedArgs& sh,
                           int32_t* dev_status, double* total_out, hipStream_t s);
-hipError_t launch_finish(int prec, const void* w, const WArgs& wa, const ZArgs& za,
+hipError_t launch_finish(int prec, const WSource& src, const WArgs& wa, const ZArgs& za,
                          const SharedArgs& sh, int32_t* dev_status, double* u_out, int32_t* r,
                          int vec_ok, hipStream_t s);
-hipError_t launch_materialize_w(int prec, const void* w, const WArgs& wa, const SharedArgs& sh,
+hipError_t launch_materialize_w(int prec, const WSource& src, const WArgs& wa, const SharedArgs& sh,
                                 double* W, int vec_ok, hipStream_t s);
 hipError_t launch_materialize_u(const ZArgs& za, const SharedArgs& sh, double* u, hipStream_t s);
-hipError_t launch_map_fused(int prec, const void* w, const WArgs& wa, const ZArgs& za,
+hipError_t launch_map_fused(int prec, const WSource& src, const WArgs& wa, const ZArgs& za,
                             const SharedArgs& sh, double* u_out, int32_t* r, int vec_ok,
                             hipStream_t s);
 hipError_t launch_map_w(const double* W, int64_t M, const double* u, int64_t N, int32_t* r,

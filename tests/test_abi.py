@@ -32,7 +32,7 @@ def test_header_declares_entry_points():
     names = declared_functions()
     for n in ["dcr_workspace_bytes", "dcr_cumulative_weights", "dcr_sorted_uniforms",
               "dcr_inverse_cmf", "dcr_resample", "dcr_status_string",
-              "dcr_batched_workspace_bytes", "dcr_resample_batched"]:
+              "dcr_batched_workspace_bytes", "dcr_resample_batched", "dcr_resample_outer"]:
         assert n in names
 
 
@@ -164,6 +164,20 @@ def test_host_validation_schemes(lib):
     assert g(-1, 1, 0, 1, FAKE, None) == 1
     assert g(10, 1, 0, 1, None, None) == 1
     assert g(0, 1, 0, 1, None, None) == 0           # N = 0: no-op
+
+
+def test_host_validation_outer(lib):
+    ws = _ws(lib, 1000, 100)
+    f = lib.dcr_resample_outer
+    # every call below fails on the host, before anything is enqueued
+    assert f(FAKE, 0, FAKE, 10, 100, 1, 0, 0, 0, FAKE, None, None, None, FAKE, ws, None) == 1
+    assert f(FAKE, 10, FAKE, 0, 100, 1, 0, 0, 0, FAKE, None, None, None, FAKE, ws, None) == 1
+    assert f(None, 10, FAKE, 10, 100, 1, 0, 0, 0, FAKE, None, None, None, FAKE, ws, None) == 1
+    assert f(FAKE, 10, None, 10, 100, 1, 0, 0, 0, FAKE, None, None, None, FAKE, ws, None) == 1
+    assert f(FAKE, 1 << 20, FAKE, 1 << 12, 100, 1, 0, 0, 0, FAKE, None, None, None, FAKE, ws,
+             None) == 1                                   # Na * P above 2^31 - 1
+    assert f(FAKE, 10, FAKE, 10, 100, 1, 0, 0, 7, FAKE, None, None, None, FAKE, ws, None) == 2
+    assert f(FAKE, 10, FAKE, 10, 100, 1, 0, 0, 0, FAKE, None, None, None, FAKE, 16, None) == 3
 
 
 def test_profile_api_host(lib):

@@ -80,3 +80,16 @@ def test_batched_equals_single(oracle_mod):
     for b in range(len(Ms)):
         rb, _, _ = oracle_mod.resample(w[w_off[b]:w_off[b + 1]], Ns[b], seed=21, stream=b)
         assert r[n_off[b]:n_off[b + 1]].tolist() == rb.tolist()
+
+
+def test_binary64_weights_with_binary32_spacings(oracle_mod):
+    """resample with zkind 1 on binary64 weights is the composition of the
+    pinned stages: W of the weights, the binary32-form uniforms, the count
+    definition of the map."""
+    rng = np.random.Generator(np.random.PCG64(404))
+    w = np.outer(rng.random(30), rng.random(17)).ravel()
+    r, W, u = oracle_mod.resample(w, 400, seed=6, stream=2, zkind=1)
+    W0, _ = oracle_mod.cumulative_weights(w)
+    assert np.array_equal(W, W0)
+    assert np.array_equal(u, oracle_mod.sorted_uniforms(400, 6, 2, zkind=1))
+    assert np.array_equal(r, oracle_mod.inverse_cmf_count(W, u))
