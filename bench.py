@@ -274,6 +274,58 @@ def measure_batched(dcr, torch, dev, steps: int, warmup: int, cpu_seconds: float
     return out
 
 
+def measure_outer(dcr, torch, dev, steps: int):
+    """An EnGMF-shaped step at scale: N = 65536 particles, P = 256 likelihood
+    components, M = N*P = 2^24 weights w = a_i * b_k, draw N.  binary32 factors,
+    weights formed on the fly (dcr_resample_outer) against the same weights
+    materialised in HBM (dcr_resample); the two give identical indices."""
+    import numpy as np
+
+    import workloads
+    wl = workloads.engmf_step(N=65536, P=256)
+    a = wl.extra["a"].astype(np.float32)
+    b = wl.extra["b"].astype(np.float32)
+    Np, P = a.size, b.size
+    M = Np * P
+    at, bt = torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)
+    # a_i * b_k of binary32 factors is exact in binary64: the materialised array
+    w = torch.from_numpy(np.multiply.outer(a.astype(np.float64), b.astype(np.float64))
+                         .ravel()).to(dev)
+    ws = torch.empty(dcr.dcr_workspace_bytes(M, Np, dcr.DCR_FP64), dtype=torch.uint8,
+                     device=dev)
+    r1 = torch.empty(Np, dtype=torch.int32, device=dev)
+    r2 = torch.empty(Np, dtype=torch.int32, device=dev)
+    res = {"workload": f"engmf N={Np} x P={P} (M={M}), draw N={Np}, binary32 factors"}
+    a64, b64 = at.double(), bt.double()
+    calls = (("outer_f32", lambda k: dcr.dcr_resample_outer(at, bt, Np, k, r=r1, ws=ws)),
+             ("outer_f64", lambda k: dcr.dcr_resample_outer(a64, b64, Np, k, r=r1, ws=ws)),
+             ("array_f64", lambda k: dcr.dcr_resample(w, Np, k, r=r2, ws=ws)))
+    for name, fn in calls:
+        for k in range(2):
+            fn(k)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for k in range(steps):
+            fn(k)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        res[name] = {"ms_per_step": ms, "value": Np / (ms * 1e-3), "unit": "particles/s"}
+    dcr.dcr_profile_begin(steps * 8)
+    for k in range(steps):
+        calls[0][1](k)
+    prof = dcr.dcr_profile_end()
+    res["outer_f32"]["kernels_ms"] = {k: v[1] / v[0] for k, v in prof.items() if v[0] > 0}
+    dcr.dcr_resample_outer(a64, b64, Np, 3, r=r1, ws=ws)
+    dcr.dcr_resample(w, Np, 3, r=r2, ws=ws)
+    torch.cuda.synchronize()
+    res["outer_f64_equals_array"] = bool(torch.equal(r1, r2))
+    del w, ws
+    torch.cuda.empty_cache()
+    return res
+
+
 def cpu_baseline(wl, w_host, seconds: float):
     import numpy as np
 
@@ -308,6 +360,10 @@ def main():
     ap.add_argument("--workload", default="sparse", choices=["sparse", "equal", "engmf", "single"])
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 4096-filter batched workload reported beside the main line")
+    ap.add_argument("--no-outer", action="store_true",
+                    help="skip the structured (outer-product) EnGMF workload")
+    ap.add_argument("--outer-only", action="store_true",
+                    help="run only the structured (outer-product) EnGMF workload")
     ap.add_argument("--no-equal", action="store_true",
                     help="skip the equal-size workload reported beside the main line")
     ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
@@ -343,6 +399,9 @@ def main():
         return
     dev = torch.device("cuda:0")
     dcr.library()
+    if args.outer_only:
+        print(json.dumps({"engmf_outer": measure_outer(dcr, torch, dev, args.steps)}), flush=True)
+        return
     wl = workloads.CONFIGS[args.workload]()
 
     def measure(prec: str, steps: int, warmup: int):
@@ -472,6 +531,8 @@ def main():
     if not args.no_batched:
         out["batched"] = measure_batched(dcr, torch, dev, max(5, args.steps // 5), 2,
                                          0.0 if args.no_cpu else args.cpu_seconds / 2)
+    if not args.no_outer:
+        out["engmf_outer"] = measure_outer(dcr, torch, dev, max(5, args.steps // 5))
     if args.workload != "equal" and not args.no_equal:
         # the equal-size instance (linear-merge limit of the map), binary32 form
         wl_eq = workloads.CONFIGS["equal"]()

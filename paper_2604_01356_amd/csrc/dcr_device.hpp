@@ -241,23 +241,87 @@ __device__ __forceinline__ void src_chunk(const T* __restrict__ w, int64_t j, in
     load_chunk<T>(w + (n > 0 ? j : 0), n, vec_ok, x);
 }
 
-// Outer product: the first product's factors by one division, then walk k.
+// Outer product.  j = i P + k with 0 <= k < P, from a binary64 quotient and
+// an integer correction (exact for j < 2^52).
+template <typename T>
+__device__ __forceinline__ void outer_split(const Outer<T>& o, int64_t j, int64_t& i, int64_t& k) {
+    i = static_cast<int64_t>(static_cast<double>(j) / static_cast<double>(o.P));
+    k = j - i * o.P;
+    while (k < 0) {
+        --i;
+        k += o.P;
+    }
+    while (k >= o.P) {
+        ++i;
+        k -= o.P;
+    }
+}
+
+// The factors of one lane chunk of products, loaded ahead of their use (rows
+// of at least kLane products, so a chunk meets at most one row end): products
+// q < wq are a0 * b[k + q], the rest a1 * b[k + q - P]; products q >= n do
+// not exist and read 0.
+template <typename T>
+struct OuterRaw {
+    T a0, a1;
+    int wq, n;
+    RawChunk<T> b;
+    __device__ __forceinline__ double at(int q) const {
+        const double x = static_cast<double>(q < wq ? a0 : a1) * static_cast<double>(b.raw(q));
+        return (q < n) ? x : 0.0;
+    }
+};
+
+template <typename T>
+__device__ __forceinline__ OuterRaw<T> outer_load(const Outer<T>& o, int64_t j, int n) {
+    OuterRaw<T> r;
+    int64_t i = 0, k = 0;
+    if (n > 0) outer_split(o, j, i, k);
+    const int64_t room = o.P - k;
+    r.wq = (room < kLane) ? static_cast<int>(room) : kLane;
+    r.n = n;
+    // every load reads a valid element (the first product's factors stand in
+    // for what does not exist), and no loaded value is used before the sum,
+    // so the loads of several chunks stay in flight together
+    r.a0 = o.a[i];
+    r.a1 = o.a[(r.wq < n) ? i + 1 : i];
+    if (n == kLane && r.wq == kLane) {
+        r.b = load_raw_any<T>(o.b + k);
+    } else {
+        constexpr int kPer = (sizeof(T) == 4) ? 4 : 2;
+#pragma unroll
+        for (int q = 0; q < kLane; ++q) {
+            const int64_t kq = (q >= n) ? k : ((q < r.wq) ? k + q : k + q - o.P);
+            r.b.v[q / kPer][q % kPer] = o.b[kq];
+        }
+    }
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ RawChunk<double> outer_products(const OuterRaw<T>& r) {
+    RawChunk<double> rc;
+#pragma unroll
+    for (int q = 0; q < kLane; ++q) rc.v[q / 2][q % 2] = r.at(q);
+    return rc;
+}
+
+// Products j .. j+n-1 (n <= 0: none), zero-padded to a chunk.
 template <typename T>
 __device__ __forceinline__ RawChunk<double> src_raw_n(const Outer<T>& o, int64_t j, int n) {
+    if (o.P >= kLane) return outer_products(outer_load(o, j, n));
+    // rows shorter than a chunk: product q is a[i + (k+q) / P] * b[(k+q) % P];
+    // every load reads a valid element (the first product's for q >= n)
     RawChunk<double> rc;
-    int64_t i = (n > 0) ? j / o.P : 0;
-    int64_t k = (n > 0) ? j - i * o.P : 0;
+    int64_t i = 0, k = 0;
+    if (n > 0) outer_split(o, j, i, k);
+    const uint32_t P = static_cast<uint32_t>(o.P);
 #pragma unroll
     for (int q = 0; q < kLane; ++q) {
-        double x = 0.0;
-        if (q < n) {
-            x = static_cast<double>(o.a[i]) * static_cast<double>(o.b[k]);
-            if (++k == o.P) {
-                k = 0;
-                ++i;
-            }
-        }
-        rc.v[q / 2][q % 2] = x;
+        const uint32_t kq = (q < n) ? static_cast<uint32_t>(k) + q : static_cast<uint32_t>(k);
+        const uint32_t di = kq / P;
+        const double x = static_cast<double>(o.a[i + di]) * static_cast<double>(o.b[kq - di * P]);
+        rc.v[q / 2][q % 2] = (q < n) ? x : 0.0;
     }
     return rc;
 }

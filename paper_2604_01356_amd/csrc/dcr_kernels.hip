@@ -286,20 +286,41 @@ __device__ __forceinline__ void reduce_w_block_outer(const Outer<T>& o, const WA
     const int64_t j00 = b * kWBlock + row * kSub + lane * kLane;
     double lt[kWIters];
     double mn = 0.0;
-#pragma unroll 2
-    for (int it = 0; it < kWIters; ++it) {
-        const int64_t j0 = j00 + static_cast<int64_t>(it) * kRows * kSub;
-        const RawChunk<double> rc = src_raw_n(o, j0, clamp_count(wa.M - j0, kLane));
-        const double ct = raw_sum<double>(rc, mn);
+    if (o.P >= kLane) {
+        // the factors of kU chunks are loaded before any product is summed
+        constexpr int kU = (sizeof(T) == 4) ? kWIters : kWIters / 4;
+#pragma unroll 1
+        for (int h = 0; h < kWIters; h += kU) {
+            OuterRaw<T> raw[kU];
 #pragma unroll
-        for (int q = 0; q < kWIters; ++q)
-            if (q == it) lt[q] = ct;
+            for (int u = 0; u < kU; ++u) {
+                const int64_t j0 = j00 + static_cast<int64_t>(h + u) * kRows * kSub;
+                raw[u] = outer_load(o, j0, clamp_count(wa.M - j0, kLane));
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const double ct = raw_sum<double>(outer_products(raw[u]), mn);
+#pragma unroll
+                for (int q = 0; q < kWIters; ++q)
+                    if (q == h + u) lt[q] = ct;
+            }
+        }
+    } else {
+#pragma unroll 1
+        for (int it = 0; it < kWIters; ++it) {
+            const int64_t j0 = j00 + static_cast<int64_t>(it) * kRows * kSub;
+            const RawChunk<double> rc = src_raw_n(o, j0, clamp_count(wa.M - j0, kLane));
+            const double ct = raw_sum<double>(rc, mn);
+#pragma unroll
+            for (int q = 0; q < kWIters; ++q)
+                if (q == it) lt[q] = ct;
+        }
     }
     reduce_w_epilogue(lt, (mn < 0.0) ? 1 : 0, wa, b, sb0);
 }
 
 template <typename T, int P>
-__global__ __launch_bounds__(kThreads) void k_reduce_outer(Outer<T> o, WArgs wa, ZArgs za) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_reduce_outer(Outer<T> o, WArgs wa, ZArgs za) {
     __shared__ __attribute__((aligned(16))) unsigned char sb0[ReduceSmem<double>::kBuf0];
     if (static_cast<int64_t>(blockIdx.x) < za.nb) {
         double* lane_tot = reinterpret_cast<double*>(sb0);

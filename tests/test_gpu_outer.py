@@ -42,7 +42,9 @@ def _factors(Na, P, seed, dtype):
 
 # (Na, P, N): the EnGMF step shape (one finishing launch), a large sparse case
 # (carries + map), a dense case (merge) and ragged sizes
-CASES = [(2000, 64, 2000), (20000, 1000, 3000), (3000, 7, 20000), (1, 1, 5), (977, 33, 1)]
+# and the large EnGMF-shaped step timed beside the main measurement
+CASES = [(2000, 64, 2000), (20000, 1000, 3000), (3000, 7, 20000), (1, 1, 5), (977, 33, 1),
+         (65536, 256, 65536)]
 
 
 @pytest.mark.parametrize("Na,P,N", CASES)

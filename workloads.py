@@ -61,7 +61,8 @@ def engmf_step(N: int = 2000, P: int = 64, data_seed: int = 1002) -> Workload:
     b = rng.dirichlet(np.full(P, 0.5))
     w = (a[:, None] * b[None, :]).reshape(-1)
     return Workload(f"engmf_N{N}_P{P}", N * P, N, w,
-                    description=f"EnGMF-shaped M={N * P} (N={N} x P={P}), draw N={N}")
+                    description=f"EnGMF-shaped M={N * P} (N={N} x P={P}), draw N={N}",
+                    extra={"a": a, "b": b})
 
 
 def sparse_mass(M: int = 1 << 26, N: int = 1 << 14, sigma: float = 5.0,
