@@ -55,6 +55,9 @@ struct ReduceSmem {
     static constexpr int kBuf0 = kBuf > kEpi ? kBuf : kEpi;
 };
 
+// s_waitcnt lgkmcnt(0) with vmcnt and expcnt left at their maxima
+constexpr int kWaitLdsOnly = 0xC07F;
+
 __device__ __forceinline__ void wait_vm(int outstanding) {
     // s_waitcnt with vmcnt = outstanding (0..15), expcnt and lgkmcnt left at max
     __builtin_amdgcn_sched_barrier(0);
@@ -231,11 +234,49 @@ __device__ __forceinline__ void reduce_w_block(const Tin* __restrict__ w, const 
             }
             // NaN and +inf reach the block total (checked below); negatives the minimum
             bad = (mn < 0.0f) ? 1 : 0;
+        } else if (full) {
+            // a block that starts off a 16-byte boundary (a filter of a batch
+            // may start at any element): each wave loads its round as
+            // coalesced 16-byte pieces of element-aligned addresses, two
+            // rounds ahead in registers, and passes them through its own LDS
+            // region into the lane-chunk layout of the path above
+            done = true;
+            const int wv = t >> 6;
+            const int l64 = t & 63;
+            const float* src = reinterpret_cast<const float*>(w) + blk0 + wv * kWaveRoundF32;
+            float* const region = reinterpret_cast<float*>(sb0) + wv * kWaveRoundF32;
+            f32x4 ring[DEPTH + 1][kLane / 4];
+            auto fetch = [&](int it, f32x4 (&dst)[kLane / 4]) {
+                const float* g0 = src + it * (kWaves * kWaveRoundF32);
+#pragma unroll
+                for (int k = 0; k < kLane / 4; ++k)
+                    __builtin_memcpy(&dst[k], g0 + k * 256 + l64 * 4, sizeof(f32x4));
+            };
+#pragma unroll
+            for (int it = 0; it < DEPTH; ++it) fetch(it, ring[it]);
+            float mn = 0.0f;
+#pragma unroll
+            for (int it = 0; it < kWIters; ++it) {
+                if (it + DEPTH < kWIters) fetch(it + DEPTH, ring[(it + DEPTH) % (DEPTH + 1)]);
+#pragma unroll
+                for (int k = 0; k < kLane / 4; ++k)
+                    *reinterpret_cast<f32x4*>(region + k * 256 + l64 * 4) = ring[it % (DEPTH + 1)][k];
+                __builtin_amdgcn_s_waitcnt(kWaitLdsOnly);   // the wave's writes are done
+                __builtin_amdgcn_wave_barrier();
+                const f32x4* mine = reinterpret_cast<const f32x4*>(region + l64 * kLane);
+                RawChunk<float> rc;
+#pragma unroll
+                for (int k = 0; k < kLane / 4; ++k) rc.v[k] = mine[k];
+                if (it == 0) mn = rc.raw(0);
+                lt[it] = raw_sum<float>(rc, mn);
+                __builtin_amdgcn_wave_barrier();
+            }
+            bad = (mn < 0.0f) ? 1 : 0;
         }
     }
     if (full && !done) {
-        // binary64, or binary32 that is not 16-byte aligned: lane-strided
-        // vector loads (element-aligned), the next round issued before summing
+        // binary64: lane-strided vector loads (element-aligned), the next
+        // round issued before summing
         const Tin* base = w + blk0 + row * kSub + lane * kLane;
         Tin mn = static_cast<Tin>(0);
         RawChunk<Tin> cur = load_raw_any<Tin>(base);
@@ -319,15 +360,36 @@ __device__ __forceinline__ void reduce_w_block_outer(const Outer<T>& o, const WA
     reduce_w_epilogue(lt, (mn < 0.0) ? 1 : 0, wa, b, sb0);
 }
 
+// Workgroup order of the reduce launches.  Of nz spacing tiles and nw weight
+// tiles, the kind with fewer tiles is spread evenly among the other (one in
+// every p workgroups), so that each CU mixes the ALU-bound spacing work with
+// the HBM-bound weight stream instead of running the two one after the other.
+// Workgroup i maps to exactly one tile: is_z tells the kind, idx its index.
+struct TileRole {
+    bool is_z;
+    int64_t idx;
+};
+
+__device__ __forceinline__ TileRole tile_role(int64_t i, int64_t nz, int64_t nw) {
+    const bool z_minor = nz <= nw;
+    const int64_t nminor = z_minor ? nz : nw;
+    if (nminor == 0) return TileRole{nz > 0, i};
+    const int64_t p = (nz + nw) / nminor;   // >= 2
+    const int64_t k = i / p;
+    if (i % p == p - 1 && k < nminor) return TileRole{z_minor, k};
+    return TileRole{!z_minor, i - (k < nminor ? k : nminor)};
+}
+
 template <typename T, int P>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_reduce_outer(Outer<T> o, WArgs wa, ZArgs za) {
     __shared__ __attribute__((aligned(16))) unsigned char sb0[ReduceSmem<double>::kBuf0];
-    if (static_cast<int64_t>(blockIdx.x) < za.nb) {
+    const TileRole role = tile_role(blockIdx.x, za.nb, wa.nb);
+    if (role.is_z) {
         double* lane_tot = reinterpret_cast<double*>(sb0);
-        reduce_z_block<P>(za, blockIdx.x, lane_tot, lane_tot + kThreads);
+        reduce_z_block<P>(za, role.idx, lane_tot, lane_tot + kThreads);
         return;
     }
-    reduce_w_block_outer<T>(o, wa, static_cast<int64_t>(blockIdx.x) - za.nb, sb0);
+    reduce_w_block_outer<T>(o, wa, role.idx, sb0);
 }
 
 template <typename Tin, int P>
@@ -336,12 +398,13 @@ __global__ __launch_bounds__(kThreads) void k_reduce(const Tin* __restrict__ w, 
     __shared__ __attribute__((aligned(16))) unsigned char sb0[ReduceSmem<Tin>::kBuf0];
     __shared__ __attribute__((aligned(16))) unsigned char sb1[ReduceSmem<Tin>::kBuf];
     __shared__ __attribute__((aligned(16))) unsigned char sb2[ReduceSmem<Tin>::kBuf];
-    if (static_cast<int64_t>(blockIdx.x) < za.nb) {
+    const TileRole role = tile_role(blockIdx.x, za.nb, wa.nb);
+    if (role.is_z) {
         double* lane_tot = reinterpret_cast<double*>(sb0);
-        reduce_z_block<P>(za, blockIdx.x, lane_tot, lane_tot + kThreads);
+        reduce_z_block<P>(za, role.idx, lane_tot, lane_tot + kThreads);
         return;
     }
-    reduce_w_block<Tin>(w, wa, static_cast<int64_t>(blockIdx.x) - za.nb, vec_ok, sb0, sb1, sb2);
+    reduce_w_block<Tin>(w, wa, role.idx, vec_ok, sb0, sb1, sb2);
 }
 
 // ---------------------------------------------------------------------------
@@ -1415,15 +1478,17 @@ __device__ __forceinline__ int aligned16_flag(const void* p) {
     return (reinterpret_cast<uintptr_t>(p) & 15) == 0 ? 1 : 0;
 }
 
-// Workgroups [0, zt_cap) draw spacing blocks, the rest reduce weight blocks.
+// zt_cap workgroups draw spacing blocks and wt_cap reduce weight blocks,
+// interleaved by tile_role.
 template <typename Tin, int P>
 __global__ __launch_bounds__(kThreads) void k_reduce_batched(const Tin* __restrict__ w, BatchArgs ba) {
     __shared__ __attribute__((aligned(16))) unsigned char sb0[ReduceSmem<Tin>::kBuf0];
     __shared__ __attribute__((aligned(16))) unsigned char sb1[ReduceSmem<Tin>::kBuf];
     __shared__ __attribute__((aligned(16))) unsigned char sb2[ReduceSmem<Tin>::kBuf];
     if (ba.head[0] != kStatusOk) return;
-    int64_t tile = blockIdx.x;
-    if (tile < ba.zt_cap) {
+    const TileRole role = tile_role(blockIdx.x, ba.zt_cap, ba.wt_cap);
+    const int64_t tile = role.idx;
+    if (role.is_z) {
         if (tile >= ba.zt_base[ba.B]) return;
         const int b = find_segment(ba.zt_base, ba.B, tile);
         const ZArgs za = seg_zargs(ba, b);
@@ -1431,7 +1496,6 @@ __global__ __launch_bounds__(kThreads) void k_reduce_batched(const Tin* __restri
         reduce_z_block<P>(za, tile - ba.zt_base[b], lane_tot, lane_tot + kThreads);
         return;
     }
-    tile -= ba.zt_cap;
     if (tile >= ba.wt_base[ba.B]) return;
     const int b = find_segment(ba.wt_base, ba.B, tile);
     const WArgs wa = seg_wargs(ba, b);

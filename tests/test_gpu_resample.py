@@ -228,3 +228,29 @@ def test_large_n_dense(dev, dcr):
     assert np.all((j == 0) | (Wg[np.maximum(j - 1, 0)] < ug[idx]))
     u_o = oracle.sorted_uniforms(N, 3, 7, zkind=1)
     assert np.max(np.abs(ug - u_o)) <= DU_FP32
+
+
+@pytest.mark.parametrize("dtype,shift", [(np.float32, 1), (np.float32, 2), (np.float32, 3),
+                                         (np.float64, 1), (np.float64, 3)])
+def test_weights_off_16_byte_boundary(dev, dcr, dtype, shift):
+    """Weights that start off a 16-byte boundary (a view into a larger buffer)
+    take other load paths; the result must equal the aligned call bit for bit,
+    in the sparse and the dense regime."""
+    rng = np.random.Generator(np.random.PCG64(40 + shift))
+    M = 5 * 32768 + 1234                      # several full blocks and a ragged one
+    w = np.exp(rng.normal(0.0, 2.0, M)).astype(dtype)
+    buf = torch.zeros(M + 8, dtype=torch.from_numpy(w).dtype, device=dev)
+    buf[shift:shift + M] = _t(w, dev)
+    view = buf[shift:shift + M]
+    assert view.data_ptr() % 16 != 0
+    aligned = _t(w, dev)
+    for N in (777, 120000):
+        for x in (view, aligned):
+            assert x.is_contiguous()
+        W0 = torch.empty(M, dtype=torch.float64, device=dev)
+        W1 = torch.empty(M, dtype=torch.float64, device=dev)
+        r0 = dcr.dcr_resample(aligned, N, 3, 0, W_out=W0)
+        r1 = dcr.dcr_resample(view, N, 3, 0, W_out=W1)
+        torch.cuda.synchronize()
+        assert np.array_equal(r0.cpu().numpy(), r1.cpu().numpy())
+        assert np.array_equal(W0.cpu().numpy(), W1.cpu().numpy())
