@@ -361,20 +361,26 @@ __device__ __forceinline__ void reduce_w_block_outer(const Outer<T>& o, const WA
 }
 
 // Workgroup order of the reduce launches.  Of nz spacing tiles and nw weight
-// tiles, the kind with fewer tiles is spread evenly among the other (one in
-// every p workgroups), so that each CU mixes the ALU-bound spacing work with
-// the HBM-bound weight stream instead of running the two one after the other.
+// tiles, the kind with fewer tiles is spread among the other, one in every p
+// workgroups, so that each CU mixes the ALU-bound spacing work with the
+// HBM-bound weight stream instead of running the two one after the other.
+// p is odd, so that consecutive tiles of the spread kind land on different
+// XCDs (workgroups go to the 8 XCDs in turn).  Spacing tiles that fit at one
+// per CU go first instead: spread to the end of the launch, a slow (binary64)
+// spacing tile would become its tail.
 // Workgroup i maps to exactly one tile: is_z tells the kind, idx its index.
 struct TileRole {
     bool is_z;
     int64_t idx;
 };
+constexpr int64_t kTileFirstMax = 256;   // compute units of the chip
 
 __device__ __forceinline__ TileRole tile_role(int64_t i, int64_t nz, int64_t nw) {
     const bool z_minor = nz <= nw;
     const int64_t nminor = z_minor ? nz : nw;
     if (nminor == 0) return TileRole{nz > 0, i};
-    const int64_t p = (nz + nw) / nminor;   // >= 2
+    const int64_t spread = (nz + nw) / nminor;   // >= 2
+    const int64_t p = (z_minor && nz <= kTileFirstMax) ? 1 : spread - (1 - (spread & 1));
     const int64_t k = i / p;
     if (i % p == p - 1 && k < nminor) return TileRole{z_minor, k};
     return TileRole{!z_minor, i - (k < nminor ? k : nminor)};
