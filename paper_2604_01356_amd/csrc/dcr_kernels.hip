@@ -1491,22 +1491,26 @@ __global__ __launch_bounds__(kThreads) void k_reduce_batched(const Tin* __restri
     __shared__ __attribute__((aligned(16))) unsigned char sb0[ReduceSmem<Tin>::kBuf0];
     __shared__ __attribute__((aligned(16))) unsigned char sb1[ReduceSmem<Tin>::kBuf];
     __shared__ __attribute__((aligned(16))) unsigned char sb2[ReduceSmem<Tin>::kBuf];
-    if (ba.head[0] != kStatusOk) return;
+    // the plan's status, the tile count and the tile's filter are looked up
+    // together (the plan writes every base, so the search stays in range even
+    // when it failed); nothing found is used before the status is checked
     const TileRole role = tile_role(blockIdx.x, ba.zt_cap, ba.wt_cap);
     const int64_t tile = role.idx;
+    const int plan = ba.head[0];
+    const int64_t* base = role.is_z ? ba.zt_base : ba.wt_base;
+    const int64_t ntiles = base[ba.B];
+    const int b = find_segment(base, ba.B, tile);
+    const int64_t first = base[b];
+    if (plan != kStatusOk || tile >= ntiles) return;
     if (role.is_z) {
-        if (tile >= ba.zt_base[ba.B]) return;
-        const int b = find_segment(ba.zt_base, ba.B, tile);
         const ZArgs za = seg_zargs(ba, b);
         double* lane_tot = reinterpret_cast<double*>(sb0);
-        reduce_z_block<P>(za, tile - ba.zt_base[b], lane_tot, lane_tot + kThreads);
+        reduce_z_block<P>(za, tile - first, lane_tot, lane_tot + kThreads);
         return;
     }
-    if (tile >= ba.wt_base[ba.B]) return;
-    const int b = find_segment(ba.wt_base, ba.B, tile);
     const WArgs wa = seg_wargs(ba, b);
     const Tin* ws = w + ba.w_off[b];
-    reduce_w_block<Tin>(ws, wa, tile - ba.wt_base[b], aligned16_flag(ws), sb0, sb1, sb2);
+    reduce_w_block<Tin>(ws, wa, tile - first, aligned16_flag(ws), sb0, sb1, sb2);
 }
 
 // One workgroup per filter: its block-total scans, totals and status.
@@ -1589,17 +1593,30 @@ __device__ void map_seg_chunk(const Tin* __restrict__ w, const WArgs& wa, const 
     const int t = threadIdx.x;
     const int64_t N = za.N;
     const int64_t i0 = c * kSegU;
-    const int nu = static_cast<int>((N - i0 < kSegU) ? N - i0 : kSegU);
-    const bool ok = sh.status[0] == kStatusOk;
-    if (!ok) {
+    const int nu = static_cast<int>((N - i0 < kSegU) ? N - i0 : kSegU);   // >= 1
+    // the filter's status and totals, and the spacing prefixes and spacing
+    // block ends of the chunk's draws, in one round trip: every address is in
+    // range whatever the status says
+    const int status = sh.status[0];
+    const double total = sh.totals[0];
+    const double ztot = sh.totals[1];
+    double zr[kSegPer], zlo[kSegPer], zhi[kSegPer];
+#pragma unroll
+    for (int k = 0; k < kSegPer; ++k) {
+        const int pos = t + k * kThreads;
+        const int64_t i = i0 + ((pos < nu) ? pos : nu - 1);
+        const int64_t g = i / kZBlock;
+        zr[k] = za.zrel[i];
+        zlo[k] = (g == 0) ? 0.0 : za.beta[g - 1];
+        zhi[k] = za.beta[g];
+    }
+    if (status != kStatusOk) {
         for (int k = 0; k < kSegPer; ++k) {
             const int pos = t + k * kThreads;
             if (pos < nu) r[i0 + pos] = -1;
         }
         return;
     }
-    const double total = sh.totals[0];
-    const double ztot = sh.totals[1];
     const int64_t nb = wa.nb;
     const int64_t kstride = (nb + kSegBetaLds - 1) / kSegBetaLds;
     const int ns = static_cast<int>((nb + kstride - 1) / kstride);
@@ -1615,7 +1632,8 @@ __device__ void map_seg_chunk(const Tin* __restrict__ w, const WArgs& wa, const 
     for (int k = 0; k < kSegPer; ++k) {
         const int pos = t + k * kThreads;
         xs[k] = __builtin_huge_val();
-        if (pos < nu) xs[k] = threshold_for(uniform_at(za, ztot, i0 + pos), total);
+        if (pos < nu)
+            xs[k] = threshold_for(uniform_of(zr[k], i0 + pos, N, zlo[k], zhi[k], ztot), total);
         L.sx[pos] = xs[k];
     }
     lds_barrier();
@@ -1853,13 +1871,17 @@ __global__ __launch_bounds__(kThreads) void k_map_batched(const Tin* __restrict_
                                                           int32_t* __restrict__ r,
                                                           int32_t* dev_status) {
     __shared__ SegLds<kSegU, kSegPass> L;
+    // the plan's status, the chunk count and the chunk's filter are looked up
+    // together (the plan writes every base, so the search stays in range even
+    // when it failed); nothing found is used before the status is checked
     const int plan = ba.head[0];
+    const int64_t nchunks = ba.mc_base[ba.B];
+    const int64_t c = blockIdx.x;
+    const int b = find_segment(ba.mc_base, ba.B, c);
     if (blockIdx.x == 0 && threadIdx.x == 0 && dev_status)
         *dev_status = (plan != kStatusOk) ? plan : ba.head[1];
     if (plan != kStatusOk) return;
-    const int64_t c = blockIdx.x;
-    if (c >= ba.mc_base[ba.B]) return;
-    const int b = find_segment(ba.mc_base, ba.B, c);
+    if (c >= nchunks) return;
     const Tin* ws = w + ba.w_off[b];
     map_seg_chunk<Tin, kSegU, kSegPass>(ws, seg_wargs(ba, b), seg_zargs(ba, b), seg_shared(ba, b),
                        r + ba.n_off[b], c - ba.mc_base[b], L);
