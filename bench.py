@@ -352,6 +352,90 @@ def cpu_baseline(wl, w_host, seconds: float):
     }, r0
 
 
+def cpu_paper_algorithm(wl, w_host, seconds: float):
+    """The paper's own sequential method on the host, for a second CPU row:
+    the plain running sum of Eq. 3 divided by the total, Alg. 1 with a plain
+    running sum of the oracle's spacings, and the oracle's literal Alg. 5."""
+    import numpy as np
+
+    import oracle
+    w = np.asarray(w_host, dtype=np.float64)
+    times = []
+    t_end = time.perf_counter() + seconds
+    while True:
+        t0 = time.perf_counter()
+        S = np.cumsum(w)
+        W = S / S[-1]
+        Z = np.cumsum(oracle.exponential_spacings(wl.N, seed=0, stream=0))
+        u = Z[:wl.N] / Z[wl.N]
+        oracle.dac(W, u)
+        times.append(time.perf_counter() - t0)
+        if time.perf_counter() >= t_end or len(times) >= 50:
+            break
+    t = float(np.median(times))
+    return {
+        "value": wl.N / t,
+        "unit": "particles/s",
+        "cores": 1,
+        "kind": "paper algorithm (plain running sums, Alg. 1, Alg. 5)",
+        "sample": f"{len(times)} end-to-end runs of the same workload (M={wl.M}, N={wl.N}), "
+                  f"median {t:.3f} s each, single thread",
+    }
+
+
+def measure_small(dcr, torch, dev, reps: int = 200):
+    """The two small configurations are latency-bound: microseconds per
+    dcr_resample call, eager and replayed from a captured HIP graph."""
+    import numpy as np
+
+    import workloads
+    res = {}
+    for wl in (workloads.small_single(), workloads.engmf_step()):
+        for prec in ("f64", "f32"):
+            w = torch.from_numpy(wl.w64 if prec == "f64" else wl.w32).to(dev)
+            p = dcr.precision_of(w)
+            ws = torch.empty(dcr.dcr_workspace_bytes(wl.M, wl.N, p), dtype=torch.uint8,
+                             device=dev)
+            r_e = torch.empty(wl.N, dtype=torch.int32, device=dev)
+            r_g = torch.empty(wl.N, dtype=torch.int32, device=dev)
+
+            def timed(fn):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(reps):
+                    fn()
+                e1.record()
+                torch.cuda.synchronize()
+                return e0.elapsed_time(e1) / reps * 1e3
+
+            for _ in range(3):
+                dcr.dcr_resample(w, wl.N, 0, r=r_e, ws=ws)
+            torch.cuda.synchronize()
+            eager_us = timed(lambda: dcr.dcr_resample(w, wl.N, 0, r=r_e, ws=ws))
+            s = torch.cuda.Stream()
+            s.wait_stream(torch.cuda.current_stream())
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.stream(s):
+                dcr.dcr_resample(w, wl.N, 0, r=r_g, ws=ws)
+                torch.cuda.synchronize()
+                with torch.cuda.graph(g, stream=s):
+                    dcr.dcr_resample(w, wl.N, 0, r=r_g, ws=ws)
+            torch.cuda.current_stream().wait_stream(s)
+            g.replay()
+            torch.cuda.synchronize()
+            graph_us = timed(g.replay)
+            res[f"{wl.name}/{prec}"] = {
+                "M": wl.M, "N": wl.N,
+                "us_per_call_eager": eager_us,
+                "us_per_call_graph": graph_us,
+                "graph_equals_eager": bool(torch.equal(r_g, r_e)),
+            }
+            del g, ws
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -362,6 +446,8 @@ def main():
                     help="skip the 4096-filter batched workload reported beside the main line")
     ap.add_argument("--no-outer", action="store_true",
                     help="skip the structured (outer-product) EnGMF workload")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the two small, latency-bound configurations")
     ap.add_argument("--outer-only", action="store_true",
                     help="run only the structured (outer-product) EnGMF workload")
     ap.add_argument("--no-equal", action="store_true",
@@ -517,6 +603,7 @@ def main():
     if not args.no_cpu:
         cb, r_or = cpu_baseline(wl, w_host, args.cpu_seconds)
         out["cpu_baseline"] = cb
+        out["cpu_paper_algorithm"] = cpu_paper_algorithm(wl, w_host, args.cpu_seconds / 2)
         out["mismatches_vs_oracle_seed0"] = int(np.sum(r_gpu != r_or))
         if W_gpu is not None:
             # the binary32-input result against the oracle on the binary64 weights
@@ -533,6 +620,8 @@ def main():
                                          0.0 if args.no_cpu else args.cpu_seconds / 2)
     if not args.no_outer:
         out["engmf_outer"] = measure_outer(dcr, torch, dev, max(5, args.steps // 5))
+    if not args.no_small:
+        out["small_configs"] = measure_small(dcr, torch, dev)
     if args.workload != "equal" and not args.no_equal:
         # the equal-size instance (linear-merge limit of the map), binary32 form
         wl_eq = workloads.CONFIGS["equal"]()
