@@ -383,6 +383,43 @@ def cpu_paper_algorithm(wl, w_host, seconds: float):
     }
 
 
+def measure_stages(dcr, torch, dev, wl, prec: str, reps: int):
+    """The three stages called separately on the main workload, each
+    materialising its output (W, then u, then r from that W and u)."""
+    w_host = wl.w32 if prec == "f32" else wl.w64
+    w = torch.from_numpy(w_host).to(dev)
+    p = dcr.precision_of(w)
+    ws = torch.empty(dcr.dcr_workspace_bytes(wl.M, wl.N, p), dtype=torch.uint8, device=dev)
+    W = torch.empty(wl.M, dtype=torch.float64, device=dev)
+    tot = torch.empty(1, dtype=torch.float64, device=dev)
+    u = torch.empty(max(wl.N, 1), dtype=torch.float64, device=dev)
+    r = torch.empty(max(wl.N, 1), dtype=torch.int32, device=dev)
+    calls = {
+        "cumulative_weights": lambda: dcr.dcr_cumulative_weights(w, W=W, total=tot, ws=ws),
+        "sorted_uniforms": lambda: dcr.dcr_sorted_uniforms(wl.N, 0, 0, precision=p, u=u, ws=ws),
+        "inverse_cmf": lambda: dcr.dcr_inverse_cmf(W, u[:wl.N], r=r),
+    }
+    res = {"workload": wl.description, "precision": prec}
+    for name, fn in calls.items():
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        res[name + "_us"] = e0.elapsed_time(e1) / reps * 1e3
+    s_w = 4 if prec == "f32" else 8
+    res["cumulative_weights_gbs"] = (wl.M * (s_w + 8)) / (res["cumulative_weights_us"] * 1e-6) / 1e9
+    res["note"] = ("stage 1 reads w and writes W (M*(s_w+8) bytes, the rate above); the fused "
+                   "dcr_resample writes neither W nor u")
+    del w, ws, W, u, r
+    torch.cuda.empty_cache()
+    return res
+
+
 def measure_small(dcr, torch, dev, reps: int = 200):
     """The two small configurations are latency-bound: microseconds per
     dcr_resample call, eager and replayed from a captured HIP graph."""
@@ -446,6 +483,8 @@ def main():
                     help="skip the 4096-filter batched workload reported beside the main line")
     ap.add_argument("--no-outer", action="store_true",
                     help="skip the structured (outer-product) EnGMF workload")
+    ap.add_argument("--no-stages", action="store_true",
+                    help="skip the three stages timed as separate calls")
     ap.add_argument("--no-small", action="store_true",
                     help="skip the two small, latency-bound configurations")
     ap.add_argument("--outer-only", action="store_true",
@@ -622,6 +661,9 @@ def main():
         out["engmf_outer"] = measure_outer(dcr, torch, dev, max(5, args.steps // 5))
     if not args.no_small:
         out["small_configs"] = measure_small(dcr, torch, dev)
+    if not args.no_stages:
+        out["stages"] = measure_stages(dcr, torch, dev, wl, args.precision,
+                                       max(5, args.steps // 5))
     if args.workload != "equal" and not args.no_equal:
         # the equal-size instance (linear-merge limit of the map), binary32 form
         wl_eq = workloads.CONFIGS["equal"]()

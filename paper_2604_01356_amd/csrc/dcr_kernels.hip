@@ -1042,6 +1042,52 @@ constexpr int kWinLen = kWinSub * kSub;       // weights per window (= kThreads 
 constexpr int kMaxWin = 4;
 static_assert(kWinLen <= kBetaLds, "the window reuses the block-end stage");
 
+// Places this thread's sorted values x[next..nmine) that end in a window of
+// nwin non-decreasing values sw (those not above the window's last value, or
+// all that remain in the final window): each one's position is the count of
+// window entries below it among the first nwin-1, found by bisection for the
+// first and by galloping forward from the previous one for the others.
+// res[q] = base + position; next moves past the values placed.
+__device__ __forceinline__ void place_in_window(const double* sw, int nwin, bool final_window,
+                                                const double (&x)[kDensePer], int nmine,
+                                                int64_t base, int& next,
+                                                int32_t (&res)[kDensePer]) {
+    const double wend = sw[nwin - 1];
+    int pos = -1;
+#pragma unroll
+    for (int q = 0; q < kDensePer; ++q) {
+        if (q >= next && q < nmine && (final_window || x[q] <= wend)) {
+            const double v = x[q];
+            if (pos < 0) {
+                // count of entries below v among the first nwin-1
+                int cnt = 0;
+#pragma unroll
+                for (int step = kWinLen / 2; step >= 1; step >>= 1)
+                    if (cnt + step <= nwin - 1 && sw[cnt + step - 1] < v) cnt += step;
+                pos = cnt;
+            } else if (sw[pos] < v) {
+                // first j > pos with sw[j] >= v: gallop, then bisect
+                int lo = pos, step = 1;   // sw[lo] < v
+                while (lo + step < nwin - 1 && sw[lo + step] < v) {
+                    lo += step;
+                    step <<= 1;
+                }
+                int hi = (lo + step < nwin - 1) ? lo + step : nwin - 1;   // sw[hi] >= v
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (sw[mid] < v)
+                        lo = mid;
+                    else
+                        hi = mid;
+                }
+                pos = hi;
+            }
+            res[q] = static_cast<int32_t>(base + pos);
+            next = q + 1;
+        }
+    }
+}
+
 template <typename Src>
 __device__ __forceinline__ void k_map_dense_body(Src w, WArgs wa, ZArgs za, SharedArgs sh, double* __restrict__ u_out, int32_t* __restrict__ r, int32_t* __restrict__ wide, int per_wg) {
     using Elem = typename SrcElem<Src>::type;
@@ -1161,45 +1207,10 @@ __device__ __forceinline__ void k_map_dense_body(Src w, WArgs wa, ZArgs za, Shar
             sw[t * kLane + k] = (k < nv) ? S / total : __builtin_huge_val();
         }
         lds_barrier();
-        // entries of the window that exist, and the last one's value
+        // entries of the window that exist
         const int64_t wlen64 = wa.M - ws0 * kSub;
         const int nwin = (nw * kSub < wlen64) ? nw * kSub : static_cast<int>(wlen64);
-        const double wend = sw[nwin - 1];
-        // place this thread's draws that end in the window: u <= wend; the
-        // first by bisection of the window, the others galloping from it
-        int pos = -1;
-#pragma unroll
-        for (int q = 0; q < kDensePer; ++q) {
-            if (q >= next && q < nmine && us[q] <= wend) {
-                const double x = us[q];
-                if (pos < 0) {
-                    // count of entries below x among the first nwin-1
-                    int cnt = 0;
-#pragma unroll
-                    for (int step = kWinLen / 2; step >= 1; step >>= 1)
-                        if (cnt + step <= nwin - 1 && sw[cnt + step - 1] < x) cnt += step;
-                    pos = cnt;
-                } else if (sw[pos] < x) {
-                    // first j > pos with sw[j] >= x: gallop, then bisect
-                    int lo = pos, step = 1;   // sw[lo] < x
-                    while (lo + step < nwin - 1 && sw[lo + step] < x) {
-                        lo += step;
-                        step <<= 1;
-                    }
-                    int hi = (lo + step < nwin - 1) ? lo + step : nwin - 1;   // sw[hi] >= x
-                    while (hi - lo > 1) {
-                        const int mid = (lo + hi) >> 1;
-                        if (sw[mid] < x)
-                            lo = mid;
-                        else
-                            hi = mid;
-                    }
-                    pos = hi;
-                }
-                res[q] = static_cast<int32_t>(ws0 * kSub + pos);
-                next = q + 1;
-            }
-        }
+        place_in_window(sw, nwin, false, us, nmine, ws0 * kSub, next, res);
         lds_barrier();   // ltot and the window are rewritten by the next window
     }
     if (nmine == kDensePer && (reinterpret_cast<uintptr_t>(r + iu0) & 15) == 0) {
@@ -1337,18 +1348,118 @@ __device__ __forceinline__ int64_t lower_bound_clamped(const double* __restrict_
     return b;
 }
 
+// #{j in [0, M-1) : W_j < x} for non-decreasing W (= lower_bound_clamped(W,
+// 0, M-1, x)) by a 64-ary search of one wave: each step probes 64 evenly
+// spaced positions and keeps the stride between the last one below x and the
+// next.  Every lane of the wave must call it; all return the same value.
+__device__ __forceinline__ int64_t lower_bound_wave(const double* __restrict__ W, int64_t M,
+                                                    double x) {
+    const int lane = threadIdx.x & 63;
+    int64_t lo = 0, hi = M - 1;   // the count lies in [lo, hi]
+    while (lo < hi) {
+        const int64_t stride = (hi - lo + 63) / 64;
+        const int64_t j = lo + lane * stride;
+        const bool below = j < hi && W[j] < x;
+        const int k = __popcll(__ballot(below));
+        if (k == 0) {
+            hi = lo;
+        } else {
+            const int64_t nlo = lo + (k - 1) * stride + 1;
+            const int64_t nhi = lo + k * stride;
+            lo = nlo;
+            hi = (nhi < hi) ? nhi : hi;
+        }
+    }
+    return lo;
+}
+
+constexpr int kMapWStage = 4096;   // W entries a workgroup stages in LDS
+
 __global__ __launch_bounds__(kThreads) void k_map_w(const double* __restrict__ W, int64_t M,
                                                     const double* __restrict__ u, int64_t N,
                                                     int32_t* __restrict__ r) {
+    __shared__ double sw[kMapWStage];
     __shared__ int64_t range[2];
     const int t = threadIdx.x;
     const int64_t first = static_cast<int64_t>(blockIdx.x) * kThreads;
     const int64_t last = (first + kThreads < N ? first + kThreads : N) - 1;
-    if (t == 0) range[0] = lower_bound_clamped(W, 0, M - 1, u[first]);
-    if (t == 1) range[1] = lower_bound_clamped(W, 0, M - 1, u[last]);
-    lds_barrier();
     const int64_t i = first + t;
-    if (i <= last) r[i] = static_cast<int32_t>(lower_bound_clamped(W, range[0], range[1], u[i]));
+    const double x = (i <= last) ? u[i] : 0.0;
+    // the range of the workgroup's uniforms: waves 0 and 1 locate the first
+    // and the last one (the split of Alg. 5)
+    if (t < 128) {
+        const int64_t j = lower_bound_wave(W, M, u[(t < 64) ? first : last]);
+        if ((t & 63) == 0) range[t >> 6] = j;
+    }
+    lds_barrier();
+    const int64_t lo = range[0], hi = range[1];
+    const int64_t len = hi - lo + 1;
+    if (len <= kMapWStage) {
+        // a short range (several uniforms per weight): W[lo..hi] into LDS,
+        // each uniform located there
+        for (int64_t q = t; q < len; q += kThreads) sw[q] = W[lo + q];
+        lds_barrier();
+        if (i <= last) {
+            int a = 0, b = static_cast<int>(len) - 1;
+            while (a < b) {
+                const int m = (a + b) >> 1;
+                if (sw[m] < x)
+                    a = m + 1;
+                else
+                    b = m;
+            }
+            r[i] = static_cast<int32_t>(lo + b);
+        }
+    } else if (i <= last) {
+        r[i] = static_cast<int32_t>(lower_bound_clamped(W, lo, hi, x));
+    }
+}
+
+// Stage 3 in the dense regime (N * 4 >= M): per_wg consecutive uniforms per
+// workgroup, 16 per thread, as in k_map_dense.  Waves 0 and 1 locate the
+// first and the last uniform; the range of W between them is staged a window
+// of kWinLen values at a time, and every thread places its own uniforms in
+// it (place_in_window), the last window taking all that remain (the clamp).
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_map_w_dense(
+    const double* __restrict__ W, int64_t M, const double* __restrict__ u, int64_t N,
+    int32_t* __restrict__ r, int per_wg) {
+    __shared__ double sw[kWinLen];
+    __shared__ int64_t range[2];
+    const int t = threadIdx.x;
+    const int64_t c0 = static_cast<int64_t>(blockIdx.x) * per_wg;
+    const int64_t c1 = (c0 + per_wg < N) ? c0 + per_wg : N;
+    const int64_t iu0 = c0 + static_cast<int64_t>(t) * kDensePer;
+    const int nmine = clamp_count(c1 - iu0, kDensePer);
+    double x[kDensePer];
+#pragma unroll
+    for (int q = 0; q < kDensePer; ++q) x[q] = (q < nmine) ? u[iu0 + q] : 0.0;
+    if (t < 128) {
+        const int64_t j = lower_bound_wave(W, M, u[(t < 64) ? c0 : c1 - 1]);
+        if ((t & 63) == 0) range[t >> 6] = j;
+    }
+    lds_barrier();
+    const int64_t lo = range[0], hi = range[1];
+    int32_t res[kDensePer];
+#pragma unroll
+    for (int q = 0; q < kDensePer; ++q) res[q] = 0;
+    int next = 0;
+    for (int64_t ws0 = lo; ws0 <= hi; ws0 += kWinLen) {
+        const int nwin = static_cast<int>((hi + 1 - ws0 < kWinLen) ? hi + 1 - ws0 : kWinLen);
+        for (int k = t; k < nwin; k += kThreads) sw[k] = W[ws0 + k];
+        lds_barrier();
+        place_in_window(sw, nwin, ws0 + kWinLen > hi, x, nmine, ws0, next, res);
+        lds_barrier();   // the window is rewritten next
+    }
+    if (nmine == kDensePer && (reinterpret_cast<uintptr_t>(r + iu0) & 15) == 0) {
+        int4* dst = reinterpret_cast<int4*>(r + iu0);
+#pragma unroll
+        for (int v = 0; v < kDensePer / 4; ++v)
+            dst[v] = make_int4(res[4 * v], res[4 * v + 1], res[4 * v + 2], res[4 * v + 3]);
+    } else {
+#pragma unroll
+        for (int q = 0; q < kDensePer; ++q)
+            if (q < nmine) r[iu0 + q] = res[q];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -2081,9 +2192,13 @@ hipError_t launch_finish(int prec, const WSource& src, const WArgs& wa, const ZA
 hipError_t launch_map_w(const double* W, int64_t M, const double* u, int64_t N, int32_t* r,
                         hipStream_t s) {
     if (N <= 0) return hipSuccess;
+    if (map_is_dense(M, N)) {
+        launch(k_map_w_dense, dim3(static_cast<unsigned>(dense_chunks(M, N))), dim3(kThreads), 0,
+               s, W, M, u, N, r, dense_per_wg(M, N));
+        return hipGetLastError();
+    }
     const int64_t grid = (N + kThreads - 1) / kThreads;
-    launch(k_map_w, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s, W, M, u, N,
-                       r);
+    launch(k_map_w, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s, W, M, u, N, r);
     return hipGetLastError();
 }
 

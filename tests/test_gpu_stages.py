@@ -41,6 +41,8 @@ def _t(a, dev):
 MAP_CASES = [
     ("tiny", 1, 1), ("M1", 1, 50), ("N_gt_M", 7, 300), ("ragged", 1000, 257),
     ("wide", 100000, 1000), ("dense", 70000, 65537), ("equal", 4096, 4096),
+    # a workgroup's range near the size it stages in LDS, and a deep search
+    ("stage_edge", 65536, 4096), ("deep", 3000000, 3000),
 ]
 
 
@@ -159,3 +161,18 @@ def test_sorted_uniforms_streams(dev, dcr):
     b = dcr.dcr_sorted_uniforms(1000, seed=1, stream_id=1, device=dev).cpu().numpy()
     c = dcr.dcr_sorted_uniforms(1000, seed=1, stream_id=0, device=dev).cpu().numpy()
     assert not np.array_equal(a, b) and np.array_equal(a, c)
+
+
+def test_inverse_cmf_dense_range_across_windows(dev, dcr):
+    """Dense regime with a long run of zero weights: a workgroup whose
+    uniforms straddle the run stages its range of W in several windows."""
+    rng = np.random.default_rng(77)
+    M, N = 100000, 50000
+    w = np.exp(rng.normal(0, 1, M))
+    w[20000:45000] = 0.0
+    w[70000:70003] = 5e4                        # and a few heavy weights
+    W, _ = oracle.cumulative_weights(w)
+    u = np.sort(rng.random(N))
+    r = dcr.dcr_inverse_cmf(_t(W, dev), _t(u, dev)).cpu().numpy()
+    assert np.array_equal(r, np.searchsorted(W[:-1], u, side="left"))
+    assert not np.any((r >= 20000) & (r < 45000))
