@@ -664,8 +664,15 @@ __device__ __forceinline__ void k_materialize_w_body(Src w, WArgs wa, SharedArgs
     const int64_t blk0 = b * kWBlock;
     const int64_t j0 = blk0 + static_cast<int64_t>(s) * kSub + lane * kLane;
     const int nv = clamp_count(wa.M - j0, kLane);
+    // the weights and every base they need in one round trip (the indices
+    // are in range whatever the status says)
     double x[kLane];
     src_chunk(w, j0, nv, (vec_ok & 1) != 0, x);
+    const int status = sh.status[0];
+    const double total = sh.totals[0];
+    const double sigma = (s == 0) ? 0.0 : wa.sub_end[b * kWSubPerBlock + s - 1];
+    const double beta_b = (b == 0) ? 0.0 : wa.beta[b - 1];
+    const double beta_n = wa.beta[b];
     double p[kLane];
     p[0] = x[0];
 #pragma unroll
@@ -679,12 +686,8 @@ __device__ __forceinline__ void k_materialize_w_body(Src w, WArgs wa, SharedArgs
 #pragma unroll
     for (int k = 0; k < kRowLanes; ++k)
         if (k < lane) c = c + lv[k];
-    if (nv == 0 || sh.status[0] != kStatusOk) return;
-    const double sigma = (s == 0) ? 0.0 : wa.sub_end[b * kWSubPerBlock + s - 1];
-    const double beta_b = (b == 0) ? 0.0 : wa.beta[b - 1];
-    const double beta_n = wa.beta[b];
+    if (nv == 0 || status != kStatusOk) return;
     const int64_t jlast = ((blk0 + kWBlock < wa.M) ? blk0 + kWBlock : wa.M) - 1;
-    const double total = sh.totals[0];
     double out[kLane];
 #pragma unroll
     for (int k = 0; k < kLane; ++k) {
