@@ -229,7 +229,29 @@ def measure_batched(dcr, torch, dev, steps: int, warmup: int, cpu_seconds: float
     torch.cuda.synchronize()
     assert int(st.item()) == 0
     kernels = {k: v[1] / v[0] for k, v in prof.items() if v[0] > 0}
+    # the same call captured once in a HIP graph and replayed
+    r_g = torch.empty_like(r)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        dcr.dcr_resample_batched_ex(w, w_off, n_off, seed=0, chunk=chunk, r=r_g, ws=ws)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=side):
+            dcr.dcr_resample_batched_ex(w, w_off, n_off, seed=0, chunk=chunk, r=r_g, ws=ws)
+    torch.cuda.current_stream().wait_stream(side)
+    g.replay()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    graph_ms = e0.elapsed_time(e1) / steps
     step(0)
+    torch.cuda.synchronize()
+    graph_equal = bool(torch.equal(r_g, r))
+    del g
     r0 = r.cpu().numpy()
     red_bytes = batched_reduce_bytes(bw.w_off, bw.n_off, 4)
     achieved = red_bytes / (kernels["batch_reduce"] * 1e-3) / 1e9
@@ -241,6 +263,8 @@ def measure_batched(dcr, torch, dev, steps: int, warmup: int, cpu_seconds: float
         "ms_per_step": ms,
         "value": sumN / (ms * 1e-3),
         "unit": "particles/s",
+        "graph_ms_per_step": graph_ms,
+        "graph_equals_eager": graph_equal,
         "weights_per_s": w32.size / (ms * 1e-3),
         "step_weight_gbs": w32.nbytes / (ms * 1e-3) / 1e9,
         "kernels_ms": kernels,

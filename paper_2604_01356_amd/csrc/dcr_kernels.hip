@@ -914,23 +914,38 @@ __device__ void map_quad(Src w, const WArgs& wa, const double* sbeta, int64_t ks
             tl[q] = chunk_sum(xx);
         }
     }
-    // every lane of the quad gets the 16 chunk totals and runs the
-    // left-to-right chunk bases c_l to find the first chunk ending at >= x
-    double tall[kRowLanes];
+    // left-to-right chunk bases c_l across the quad: lane q continues from
+    // the end of lane q-1's four chunks, so the sums are the same additions in
+    // the same order as one lane running over all 16
+    const bool last_sub = (s == nsub - 1);   // its last chunk ends at beta_{b+1}
+    double base = 0.0;
+    {
+        static_assert(kQuad == 4, "four lanes per quad");
+        double start = 0.0;   // start of lane k's first chunk, k = 0, 1, 2, 3
+        auto lane_end = [&](double from) {
+            double run = from;
+#pragma unroll
+            for (int q = 0; q < kChunks; ++q) run = run + tl[q];
+            return run;
+        };
+        base = (qi == 0) ? start : base;
+        start = dpp_f64<kDppQuadBcast(0)>(lane_end(start));
+        base = (qi == 1) ? start : base;
+        start = dpp_f64<kDppQuadBcast(1)>(lane_end(start));
+        base = (qi == 2) ? start : base;
+        start = dpp_f64<kDppQuadBcast(2)>(lane_end(start));
+        base = (qi == 3) ? start : base;
+    }
+    // each lane looks for the first of its chunks ending at >= x; the first
+    // lane of the quad that finds one holds the first such chunk (the ends
+    // are non-decreasing) and takes the element level
+    int lf = -1;
+    double c = base, cf = 0.0, cprev = base;
 #pragma unroll
     for (int q = 0; q < kChunks; ++q) {
-        tall[q] = dpp_f64<kDppQuadBcast(0)>(tl[q]);
-        tall[kChunks + q] = dpp_f64<kDppQuadBcast(1)>(tl[q]);
-        tall[2 * kChunks + q] = dpp_f64<kDppQuadBcast(2)>(tl[q]);
-        tall[3 * kChunks + q] = dpp_f64<kDppQuadBcast(3)>(tl[q]);
-    }
-    const bool last_sub = (s == nsub - 1);   // its last chunk ends at beta_{b+1}
-    int lf = -1;
-    double c = 0.0, cf = 0.0, cprev = 0.0;
-#pragma unroll
-    for (int l = 0; l < kRowLanes; ++l) {
+        const int l = kChunks * qi + q;
         if (l < nl && lf < 0) {
-            const double cn = c + tall[l];
+            const double cn = c + tl[q];
             const double en =
                 (last_sub && l == nl - 1) ? beta_n : fmin(beta_b + (sigma + cn), beta_n);
             if (en >= x) {
@@ -941,11 +956,17 @@ __device__ void map_quad(Src w, const WArgs& wa, const double* sbeta, int64_t ks
             c = cn;
         }
     }
-    if (lf < 0) {  // unreachable: the sub-tile's end is >= x by the search above
+    const unsigned qmask =
+        static_cast<unsigned>(__ballot(lf >= 0) >> ((threadIdx.x & 63) & ~(kQuad - 1))) & 0xFu;
+    int owner;
+    if (qmask != 0) {
+        owner = __builtin_ctz(qmask);
+    } else {  // unreachable: the sub-tile's end is >= x by the search above
+        owner = (nl - 1) / kChunks;
         lf = nl - 1;
         cf = cprev;
     }
-    if (qi != lf / kChunks) return;
+    if (qi != owner) return;
     // ---- element level, by the lane that summed chunk lf ----
     const int64_t l0 = sub0 + static_cast<int64_t>(lf) * kLane;
     const int nv = (slen - lf * kLane < kLane) ? slen - lf * kLane : kLane;
