@@ -765,6 +765,8 @@ __global__ __launch_bounds__(kThreads) void k_materialize_u(ZArgs za, SharedArgs
 constexpr int kBetaLds = 4096;
 constexpr int kQuad = 4;
 constexpr int kUPerWG = kThreads / kQuad;
+constexpr int kFinishMaxUPQ = 4;          // draws per quad in k_finish, at most
+constexpr int64_t kFinishResident = 512;  // k_finish workgroups the chip holds at once (2 per CU)
 
 // Location of the sub-tile that holds the first weight whose cumulative sum
 // reaches x (the block and sub-tile levels of the search), for one quad.
@@ -1299,22 +1301,30 @@ __global__ __launch_bounds__(kThreads) void k_map_wide_outer(Outer<T> w, WArgs w
 // (the same scan as k_carries, so the same bits), forms the uniforms of its 64
 // draws and maps them; workgroup 0 also publishes the scans, totals and status.
 // ---------------------------------------------------------------------------
-template <typename Src>
+template <typename Src, int UPQ>
 __device__ __forceinline__ void k_finish_body(Src w, WArgs wa, ZArgs za, SharedArgs sh, int32_t* dev_status, double* __restrict__ u_out, int32_t* __restrict__ r, int vec_ok) {
+    static_assert(UPQ >= 1 && UPQ <= kFinishMaxUPQ, "draws per quad");
     __shared__ double sbeta[kBetaLds];
     __shared__ double szbeta[kFinishMaxZBlocks];
     __shared__ ScanLds L;
     const int t = threadIdx.x;
     const int qi = t & (kQuad - 1);
     const bool lead = blockIdx.x == 0;
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * kUPerWG + (t / kQuad);
+    // the workgroup's draws: UPQ rounds of 64, quad t/4 taking draw
+    // i0 + 64k + t/4 in round k
+    const int64_t i0 = static_cast<int64_t>(blockIdx.x) * kUPerWG * UPQ + (t / kQuad);
     // every independent load first: the block totals of both scans and the
-    // in-block spacing prefix of this quad's draw
+    // in-block spacing prefixes of this quad's draws
     ScanIn si[2];
     scan_load(wa.blk_tot, wa.nb, si[0]);
     scan_load(za.blk_tot, za.nb, si[1]);
     const bool spacings = za.scheme == kSchemeMultinomial;
-    const double zrel = (spacings && i < za.N) ? za.zrel[i] : 0.0;
+    double zrel[UPQ];
+#pragma unroll
+    for (int k = 0; k < UPQ; ++k) {
+        const int64_t i = i0 + static_cast<int64_t>(k) * kUPerWG;
+        zrel[k] = (spacings && i < za.N) ? za.zrel[i] : 0.0;
+    }
     const ScanOut so[2] = {{wa.blk_tot, wa.nb, sbeta, lead ? wa.beta : nullptr},
                            {za.blk_tot, za.nb, szbeta, lead ? za.beta : nullptr}};
     double tt[2];
@@ -1329,28 +1339,43 @@ __device__ __forceinline__ void k_finish_body(Src w, WArgs wa, ZArgs za, SharedA
         sh.totals[1] = ztot;
         if (dev_status) *dev_status = status;
     }
-    if (i >= za.N) return;   // the four lanes of a quad share i
-    const int64_t g = i / kZBlock;
-    const double uu = spacings ? uniform_of(zrel, i, za.N, (g == 0) ? 0.0 : szbeta[g - 1],
-                                            szbeta[g], ztot)
-                               : scheme_uniform(za, i);
-    if (u_out && qi == 0) u_out[i] = uu;
-    if (status != kStatusOk) {
-        if (qi == 0) r[i] = -1;
-        return;
+    // draw i (spacing prefix zk) of this quad
+    auto one = [&](int64_t i, double zk) {
+        const int64_t g = i / kZBlock;
+        const double uu = spacings ? uniform_of(zk, i, za.N, (g == 0) ? 0.0 : szbeta[g - 1],
+                                                szbeta[g], ztot)
+                                   : scheme_uniform(za, i);
+        if (u_out && qi == 0) u_out[i] = uu;
+        if (status != kStatusOk) {
+            if (qi == 0) r[i] = -1;
+            return;
+        }
+        const double x = threshold_for(uu, tot);
+        map_quad<Src>(w, wa, sbeta, 1, static_cast<int>(wa.nb), x, i, qi, r, vec_ok);
+    };
+    if constexpr (UPQ == 1) {
+        if (i0 < za.N) one(i0, zrel[0]);   // the four lanes of a quad share i
+    } else {
+#pragma unroll 1
+        for (int k = 0; k < UPQ; ++k) {
+            const int64_t i = i0 + static_cast<int64_t>(k) * kUPerWG;
+            if (i >= za.N) break;
+            double zk = zrel[0];   // zrel[k], selected without indexing registers
+#pragma unroll
+            for (int q = 1; q < UPQ; ++q) zk = (k == q) ? zrel[q] : zk;
+            one(i, zk);
+        }
     }
-    const double x = threshold_for(uu, tot);
-    map_quad<Src>(w, wa, sbeta, 1, static_cast<int>(wa.nb), x, i, qi, r, vec_ok);
 }
 
-template <typename Tin>
+template <typename Tin, int UPQ>
 __global__ __launch_bounds__(kThreads) void k_finish(const Tin* __restrict__ w, WArgs wa, ZArgs za, SharedArgs sh, int32_t* dev_status, double* __restrict__ u_out, int32_t* __restrict__ r, int vec_ok) {
-    k_finish_body<const Tin*>(w, wa, za, sh, dev_status, u_out, r, vec_ok);
+    k_finish_body<const Tin*, UPQ>(w, wa, za, sh, dev_status, u_out, r, vec_ok);
 }
 
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_finish_outer(Outer<T> w, WArgs wa, ZArgs za, SharedArgs sh, int32_t* dev_status, double* __restrict__ u_out, int32_t* __restrict__ r, int vec_ok) {
-    k_finish_body<Outer<T>>(w, wa, za, sh, dev_status, u_out, r, vec_ok);
+template <typename T, int UPQ>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_finish_outer(Outer<T> w, WArgs wa, ZArgs za, SharedArgs sh, int32_t* dev_status, double* __restrict__ u_out, int32_t* __restrict__ r, int vec_ok) {
+    k_finish_body<Outer<T>, UPQ>(w, wa, za, sh, dev_status, u_out, r, vec_ok);
 }
 
 // ---------------------------------------------------------------------------
@@ -2194,22 +2219,37 @@ bool finish_fits(const WArgs& wa, const ZArgs& za) {
 hipError_t launch_finish(int prec, const WSource& src, const WArgs& wa, const ZArgs& za,
                          const SharedArgs& sh, int32_t* dev_status, double* u_out, int32_t* r,
                          int vec_ok, hipStream_t s) {
-    const int64_t grid = (za.N + kUPerWG - 1) / kUPerWG;
+    // draws per quad: more than one once the workgroups of one draw per quad
+    // would exceed what the chip holds at once, so that the block scans of
+    // each workgroup serve several draws and every workgroup is resident
+    const int64_t rounds = (za.N + kUPerWG * kFinishResident - 1) / (kUPerWG * kFinishResident);
+    const int upq = (rounds <= 1) ? 1 : (rounds <= 2 ? 2 : kFinishMaxUPQ);
+    const int64_t per_wg = static_cast<int64_t>(kUPerWG) * upq;
+    const dim3 grid(static_cast<unsigned>((za.N + per_wg - 1) / per_wg));
+    const dim3 block(kThreads);
     const void* w = src.w;
+    auto go = [&](auto k1, auto k2, auto k4, auto wsrc, int vec) {
+        if (upq == 1)
+            launch(k1, grid, block, 0, s, wsrc, wa, za, sh, dev_status, u_out, r, vec);
+        else if (upq == 2)
+            launch(k2, grid, block, 0, s, wsrc, wa, za, sh, dev_status, u_out, r, vec);
+        else
+            launch(k4, grid, block, 0, s, wsrc, wa, za, sh, dev_status, u_out, r, vec);
+    };
     if (src.outer()) {
         if (prec == kPrecFP32)
-            launch(k_finish_outer<float>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s,
-                   src.outer_as<float>(), wa, za, sh, dev_status, u_out, r, 1);
+            go(k_finish_outer<float, 1>, k_finish_outer<float, 2>, k_finish_outer<float, 4>,
+               src.outer_as<float>(), 1);
         else
-            launch(k_finish_outer<double>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s,
-                   src.outer_as<double>(), wa, za, sh, dev_status, u_out, r, 1);
-    } else if (prec == kPrecFP32)
-        launch(k_finish<float>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s,
-                           static_cast<const float*>(w), wa, za, sh, dev_status, u_out, r, vec_ok);
-    else
-        launch(k_finish<double>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0,
-                           s, static_cast<const double*>(w), wa, za, sh, dev_status, u_out, r,
-                           vec_ok);
+            go(k_finish_outer<double, 1>, k_finish_outer<double, 2>, k_finish_outer<double, 4>,
+               src.outer_as<double>(), 1);
+    } else if (prec == kPrecFP32) {
+        go(k_finish<float, 1>, k_finish<float, 2>, k_finish<float, 4>,
+           static_cast<const float*>(w), vec_ok);
+    } else {
+        go(k_finish<double, 1>, k_finish<double, 2>, k_finish<double, 4>,
+           static_cast<const double*>(w), vec_ok);
+    }
     return hipGetLastError();
 }
 

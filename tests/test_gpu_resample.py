@@ -85,10 +85,12 @@ def check_against_oracle(out, w, N, seed, stream, du_cap, dW_cap):
 # |dz_i| <= 2^-22 z_i, |dZ_i| <= 2^-22 Z_i and |du_i| <= 2^-21 u_i.
 DU_FP32 = 2.0**-21
 
-# (M, N): ragged edges of lanes, sub-tiles, blocks and spacing blocks; the
+# (M, N): ragged edges of lanes, sub-tiles, blocks and spacing blocks; two
+# sparse cases with two and four draws per quad in the finishing launch; the
 # last two take the multi-launch path (N + 1 > 2^18 spacings)
 RAGGED = [(1, 5), (3, 1), (5, 0), (100, 1000), (32769, 4097), (65537, 3), (40000, 4095),
-          (300001, 8191), (100003, 262143), (70001, 300000)]
+          (300001, 8191), (4194307, 40001), (8388617, 150001), (100003, 262143),
+          (70001, 300000)]
 
 
 @pytest.mark.parametrize("M,N", RAGGED)
