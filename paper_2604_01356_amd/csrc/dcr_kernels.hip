@@ -1380,10 +1380,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
 
 // ---------------------------------------------------------------------------
 // Stage 3 alone: inverse CMF of sorted u against a given non-decreasing W.
-// Each workgroup takes 256 consecutive uniforms; its first and last uniform
-// are located in the whole of W (Alg. 2), which bounds the range every other
-// uniform of the workgroup can fall in (the split of Alg. 5); each uniform is
-// then located inside that range.
+// Each workgroup takes consecutive uniforms; its first and last uniform are
+// located in the whole of W (a 64-ary search of one wave each, Alg. 2 with a
+// wider split), which bounds the range every other uniform of the workgroup
+// can fall in (the split of Alg. 5); each uniform is then located inside that
+// range, from LDS when the range is short.  k_map_w takes 256 uniforms, one
+// per thread; k_map_w_dense (N * 4 >= M) takes the dense map's runs of 16.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int64_t lower_bound_clamped(const double* __restrict__ W, int64_t a,
                                                        int64_t b, double X) {
