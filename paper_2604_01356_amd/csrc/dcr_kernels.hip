@@ -21,6 +21,8 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "dcr_device.hpp"
 #include "dcr_internal.hpp"
 #include "dcr_launch.hpp"
@@ -654,7 +656,12 @@ __global__ __launch_bounds__(kScanThreads) void k_carries(WArgs wa, ZArgs za, Sh
 // ---------------------------------------------------------------------------
 template <typename Src>
 __device__ __forceinline__ void k_materialize_w_body(Src w, WArgs wa, SharedArgs sh, double* __restrict__ W, int vec_ok) {
+    using Elem = typename SrcElem<Src>::type;
     __shared__ double lane_tot[kThreads];
+    // a full round passes through LDS twice: its weights, loaded as coalesced
+    // 16-byte pieces, into the lane-chunk layout, then its outputs back out
+    // as coalesced 16-byte stores
+    __shared__ __attribute__((aligned(16))) double stage[kThreads * kLane];
     const int t = threadIdx.x;
     const int row = t / kRowLanes;
     const int lane = t % kRowLanes;
@@ -662,12 +669,35 @@ __device__ __forceinline__ void k_materialize_w_body(Src w, WArgs wa, SharedArgs
     const int it = blockIdx.x % kWIters;
     const int s = it * kRows + row;
     const int64_t blk0 = b * kWBlock;
+    const int64_t round0 = blk0 + static_cast<int64_t>(it) * kRows * kSub;   // j0 = round0 + 16t
     const int64_t j0 = blk0 + static_cast<int64_t>(s) * kSub + lane * kLane;
     const int nv = clamp_count(wa.M - j0, kLane);
+    const bool full = round0 + kThreads * kLane <= wa.M;   // workgroup-uniform
     // the weights and every base they need in one round trip (the indices
     // are in range whatever the status says)
     double x[kLane];
-    src_chunk(w, j0, nv, (vec_ok & 1) != 0, x);
+    if constexpr (std::is_pointer<Src>::value) {
+        if (full && (vec_ok & 1)) {
+            constexpr int kPer = 16 / sizeof(Elem);            // elements per 16-byte piece
+            constexpr int kPieces = kLane / kPer;              // pieces per thread
+            typedef Elem piece_t __attribute__((ext_vector_type(kPer)));
+            const piece_t* src = reinterpret_cast<const piece_t*>(w + round0);
+            piece_t v[kPieces];
+#pragma unroll
+            for (int m = 0; m < kPieces; ++m) v[m] = src[t + m * kThreads];
+            Elem* st = reinterpret_cast<Elem*>(stage);
+#pragma unroll
+            for (int m = 0; m < kPieces; ++m)
+                *reinterpret_cast<piece_t*>(st + (t + m * kThreads) * kPer) = v[m];
+            lds_barrier();
+#pragma unroll
+            for (int k = 0; k < kLane; ++k) x[k] = static_cast<double>(st[t * kLane + k]);
+        } else {
+            src_chunk(w, j0, nv, (vec_ok & 1) != 0, x);
+        }
+    } else {
+        src_chunk(w, j0, nv, (vec_ok & 1) != 0, x);
+    }
     const int status = sh.status[0];
     const double total = sh.totals[0];
     const double sigma = (s == 0) ? 0.0 : wa.sub_end[b * kWSubPerBlock + s - 1];
@@ -678,7 +708,7 @@ __device__ __forceinline__ void k_materialize_w_body(Src w, WArgs wa, SharedArgs
 #pragma unroll
     for (int k = 1; k < kLane; ++k) p[k] = p[k - 1] + x[k];
     lane_tot[t] = p[kLane - 1];
-    lds_barrier();
+    lds_barrier();   // also: every thread has read its weights from the stage
     double lv[kRowLanes];
 #pragma unroll
     for (int k = 0; k < kRowLanes; ++k) lv[k] = lane_tot[row * kRowLanes + k];
@@ -686,7 +716,7 @@ __device__ __forceinline__ void k_materialize_w_body(Src w, WArgs wa, SharedArgs
 #pragma unroll
     for (int k = 0; k < kRowLanes; ++k)
         if (k < lane) c = c + lv[k];
-    if (nv == 0 || status != kStatusOk) return;
+    if (status != kStatusOk) return;   // workgroup-uniform
     const int64_t jlast = ((blk0 + kWBlock < wa.M) ? blk0 + kWBlock : wa.M) - 1;
     double out[kLane];
 #pragma unroll
@@ -694,10 +724,14 @@ __device__ __forceinline__ void k_materialize_w_body(Src w, WArgs wa, SharedArgs
         const double S = (j0 + k == jlast) ? beta_n : fmin(beta_b + (sigma + (c + p[k])), beta_n);
         out[k] = S / total;
     }
-    if (nv == kLane && (vec_ok & 2)) {
-        f64x2* q = reinterpret_cast<f64x2*>(W + j0);
+    if (full && (vec_ok & 2)) {
 #pragma unroll
-        for (int v = 0; v < kLane / 2; ++v) q[v] = f64x2{out[2 * v], out[2 * v + 1]};
+        for (int k = 0; k < kLane; ++k) stage[t * kLane + k] = out[k];
+        lds_barrier();
+        const f64x2* st = reinterpret_cast<const f64x2*>(stage);
+        f64x2* q = reinterpret_cast<f64x2*>(W + round0);
+#pragma unroll
+        for (int m = 0; m < kLane / 2; ++m) q[t + m * kThreads] = st[t + m * kThreads];
     } else {
         for (int k = 0; k < nv; ++k) W[j0 + k] = out[k];
     }
