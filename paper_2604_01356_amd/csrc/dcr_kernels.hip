@@ -2,6 +2,7 @@
 // stages of divide-and-conquer multinomial resampling (Popov, Secs. I-III):
 //   k_reduce            weight-block totals (Eq. 3) and spacing-block totals
 //                       (Alg. 1), one launch, two kinds of workgroups
+//                       interleaved (tile_role)
 //   k_carries           monotone scans of the block totals, totals, validity
 //   k_materialize_w     normalised cumulative weights W (stage 1 output)
 //   k_materialize_u     sorted uniforms u (stage 2 output)
@@ -13,7 +14,10 @@
 //                       Alg. 5 laid onto the block / sub-tile / element levels
 //   k_map_dense         inverse CMF when N >= M/4: the linear merge of Alg. 4
 //   k_map_wide          the chunks k_map_dense leaves (spans too wide to merge)
-//   k_map_w             inverse CMF against a given W (stage 3 alone)
+//   k_map_w, k_map_w_dense
+//                       inverse CMF against a given W (stage 3 alone)
+// Every kernel that reads weights has an `_outer` twin for weights given as
+// an outer product a[i] * b[k], formed in registers (never read from memory).
 //   k_batch_plan, k_reduce_batched, k_carries_batched, k_map_batched
 //                       the batched form: many filters in one call
 // The summation structure that fixes the bits of W and u is described in
