@@ -237,6 +237,8 @@ def dcr_resample_outer(a, b, N: int, seed: int, stream_id: int = 0,
     _dev_tensor(b, "b")
     if a.dtype != b.dtype:
         raise TypeError("a and b must have the same dtype")
+    if a.device != b.device:
+        raise ValueError("a and b must be on the same device")
     p = precision_of(a)
     Na, P = a.numel(), b.numel()
     M = Na * P
