@@ -256,3 +256,33 @@ def test_weights_off_16_byte_boundary(dev, dcr, dtype, shift):
         torch.cuda.synchronize()
         assert np.array_equal(r0.cpu().numpy(), r1.cpu().numpy())
         assert np.array_equal(W0.cpu().numpy(), W1.cpu().numpy())
+
+
+def test_maximum_size_properties(dev, dcr):
+    """The largest M the boundary accepts (2^31 - 1 binary32 weights, 8 GB;
+    indices are int32) with N = 2^20 draws.  The oracle does not run at this
+    size; the fused indices are checked against the separately called stages
+    instead, which are bit-consistent with them: W_{r-1} < u <= W_r for every
+    draw, W non-decreasing with W_{M-1} = 1, r in range and non-decreasing."""
+    M = (1 << 31) - 1
+    N = 1 << 20
+    g = torch.Generator(device=dev)
+    g.manual_seed(9)
+    w = torch.rand(M, generator=g, device=dev, dtype=torch.float32)
+    w[M // 3:M // 3 + 100000] = 0.0            # a run of zero weights
+    r = dcr.dcr_resample(w, N, 5, 0).long()
+    W = dcr.dcr_cumulative_weights(w)
+    del w
+    u = dcr.dcr_sorted_uniforms(N, 5, 0, precision=dcr.DCR_FP32_COMP, device=dev)
+    torch.cuda.synchronize()
+    assert int(r.min()) >= 0 and int(r.max()) <= M - 1
+    assert bool(torch.all(r[1:] >= r[:-1]))
+    assert float(W[-1]) == 1.0
+    assert bool(torch.all(W[1:] >= W[:-1]))
+    Wr = W[r]
+    Wprev = torch.where(r > 0, W[(r - 1).clamp(min=0)], torch.zeros_like(Wr))
+    assert bool(torch.all((u <= Wr) | (r == M - 1)))
+    assert bool(torch.all(Wprev < u))
+    zero_run = (r >= M // 3) & (r < M // 3 + 100000)
+    assert not bool(zero_run.any())
+    print(f"  M={M} N={N}: r in [{int(r.min())}, {int(r.max())}]", flush=True)
