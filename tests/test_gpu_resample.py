@@ -286,3 +286,52 @@ def test_maximum_size_properties(dev, dcr):
     zero_run = (r >= M // 3) & (r < M // 3 + 100000)
     assert not bool(zero_run.any())
     print(f"  M={M} N={N}: r in [{int(r.min())}, {int(r.max())}]", flush=True)
+
+
+def _degenerate(kind):
+    M = 3 * 32768 + 77
+    if kind == "one_weight_first":
+        w = np.zeros(M); w[0] = 2.5
+    elif kind == "one_weight_block_edge":
+        w = np.zeros(M); w[32767] = 1e-3
+    elif kind == "one_weight_last":
+        w = np.zeros(M); w[-1] = 7.0
+    elif kind == "subnormal_f64":
+        rng = np.random.default_rng(3)
+        w = rng.integers(0, 50, M) * 5e-324     # binary64 subnormals only
+        w[w.argmax()] += 5e-324
+    elif kind == "subnormal_f32":
+        rng = np.random.default_rng(4)
+        w = (rng.random(M) * 1e-39).astype(np.float32)   # binary32 subnormals
+    elif kind == "wide_range_f64":
+        rng = np.random.default_rng(5)
+        w = 10.0 ** rng.uniform(-300, 300, M)
+    else:
+        raise ValueError(kind)
+    return w
+
+
+@pytest.mark.parametrize("kind", ["one_weight_first", "one_weight_block_edge", "one_weight_last",
+                                  "subnormal_f64", "subnormal_f32", "wide_range_f64"])
+def test_degenerate_weights(dev, dcr, kind):
+    """A single nonzero weight (first, at a block edge, last), weights that
+    are all subnormal, and weights over 600 decades: the fused call equals the
+    stages and agrees with the oracle."""
+    w = _degenerate(kind)
+    for N in (5, 2000, 200000):
+        out = run_case(dcr, dev, w, N, seed=21, stream=1)
+        if kind.startswith("one_weight"):
+            assert np.all(out["r"] == int(np.flatnonzero(w)[0]))
+        du = DU_FP32 if w.dtype == np.float32 else 1e-12
+        check_against_oracle(out, w, N, 21, 1, du, 2.0**-40)
+
+
+def test_total_overflow_flagged(dev, dcr):
+    """Finite weights whose sum overflows binary64: reported, r filled with -1."""
+    w = np.ones(100000)
+    w[[10, 50000, 99999]] = 1e308
+    st = torch.full((1,), -1, dtype=torch.int32, device=dev)
+    r = dcr.dcr_resample(_t(w, dev), 300, seed=1, dev_status=st)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 6
+    assert np.all(r.cpu().numpy() == -1)
