@@ -1565,64 +1565,84 @@ constexpr int64_t kMaxSegM = 2147483647LL;
 constexpr int64_t kMaxSegN = 2147483646LL;
 
 __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(BatchArgs ba, int32_t* dev_status) {
-    __shared__ int64_t sc[3][kPlanThreads];
-    __shared__ int64_t carry[3];
+    constexpr int kPlanWaves = kPlanThreads / 64;
+    __shared__ int64_t wtot[3][kPlanWaves];
     __shared__ int err;
     const int t = threadIdx.x;
-    if (t == 0) {
-        carry[0] = carry[1] = carry[2] = 0;
-        err = (ba.w_off[0] != 0 || ba.n_off[0] != 0) ? kStatusInvalid : kStatusOk;
+    const int lane = t & 63;
+    const int wid = t >> 6;
+    if (t == 0) err = (ba.w_off[0] != 0 || ba.n_off[0] != 0) ? kStatusInvalid : kStatusOk;
+    __syncthreads();
+    // thread t takes filters [b0, b1): their counts of weight blocks, spacing
+    // blocks and map chunks, summed
+    const int64_t B = ba.B;
+    const int64_t per = (B + kPlanThreads - 1) / kPlanThreads;
+    const int64_t b0 = (static_cast<int64_t>(t) * per < B) ? static_cast<int64_t>(t) * per : B;
+    const int64_t b1 = (b0 + per < B) ? b0 + per : B;
+    auto counts = [&](int64_t b, int64_t (&c)[3]) {
+        const int64_t M = ba.w_off[b + 1] - ba.w_off[b];
+        const int64_t N = ba.n_off[b + 1] - ba.n_off[b];
+        if (M < 1 || M > kMaxSegM || N < 0 || N > kMaxSegN) {
+            err = kStatusInvalid;
+            c[0] = c[1] = c[2] = 0;
+        } else {
+            c[0] = (M + kBatchWBlock - 1) / kBatchWBlock;
+            c[1] = (N > 0) ? (N + 1 + kBatchZBlock - 1) / kBatchZBlock : 0;
+            c[2] = (N + ba.chunk - 1) / ba.chunk;
+        }
+    };
+    int64_t sum[3] = {0, 0, 0};
+    for (int64_t b = b0; b < b1; ++b) {
+        int64_t c[3];
+        counts(b, c);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) sum[k] += c[k];
+    }
+    // exclusive scan of the thread sums: within the wave by shuffles, then
+    // the wave totals
+    int64_t incl[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        incl[k] = sum[k];
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int64_t v = __shfl_up(incl[k], d, 64);
+            if (lane >= d) incl[k] += v;
+        }
+        if (lane == 63) wtot[k][wid] = incl[k];
     }
     __syncthreads();
-    for (int64_t base = 0; base < ba.B; base += kPlanThreads) {
-        const int64_t b = base + t;
-        int64_t cnt[3] = {0, 0, 0};
-        if (b < ba.B) {
-            const int64_t M = ba.w_off[b + 1] - ba.w_off[b];
-            const int64_t N = ba.n_off[b + 1] - ba.n_off[b];
-            if (M < 1 || M > kMaxSegM || N < 0 || N > kMaxSegN) {
-                err = kStatusInvalid;
-            } else {
-                cnt[0] = (M + kBatchWBlock - 1) / kBatchWBlock;
-                cnt[1] = (N > 0) ? (N + 1 + kBatchZBlock - 1) / kBatchZBlock : 0;
-                cnt[2] = (N + ba.chunk - 1) / ba.chunk;
-            }
-        }
-        // inclusive scans of the three counts (Hillis-Steele over the workgroup)
+    int64_t base[3], total[3];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) sc[k][t] = cnt[k];
-        __syncthreads();
-        for (int off = 1; off < kPlanThreads; off <<= 1) {
-            int64_t add[3] = {0, 0, 0};
-            if (t >= off) {
+    for (int k = 0; k < 3; ++k) {
+        int64_t before = 0, all = 0;
 #pragma unroll
-                for (int k = 0; k < 3; ++k) add[k] = sc[k][t - off];
-            }
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < 3; ++k) sc[k][t] += add[k];
-            __syncthreads();
+        for (int q = 0; q < kPlanWaves; ++q) {
+            const int64_t v = wtot[k][q];
+            before += (q < wid) ? v : 0;
+            all += v;
         }
-        if (b < ba.B) {
-            ba.wt_base[b] = carry[0] + sc[0][t] - cnt[0];
-            ba.zt_base[b] = carry[1] + sc[1][t] - cnt[1];
-            ba.mc_base[b] = carry[2] + sc[2][t] - cnt[2];
-        }
-        __syncthreads();
-        if (t == kPlanThreads - 1) {
-#pragma unroll
-            for (int k = 0; k < 3; ++k) carry[k] += sc[k][t];
-        }
-        __syncthreads();
+        base[k] = before + incl[k] - sum[k];
+        total[k] = all;
     }
+    for (int64_t b = b0; b < b1; ++b) {
+        ba.wt_base[b] = base[0];
+        ba.zt_base[b] = base[1];
+        ba.mc_base[b] = base[2];
+        int64_t c[3];
+        counts(b, c);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) base[k] += c[k];
+    }
+    __syncthreads();   // every thread's error report is in
     if (t == 0) {
-        ba.wt_base[ba.B] = carry[0];
-        ba.zt_base[ba.B] = carry[1];
-        ba.mc_base[ba.B] = carry[2];
+        ba.wt_base[B] = total[0];
+        ba.zt_base[B] = total[1];
+        ba.mc_base[B] = total[2];
         int st = err;
         if (st == kStatusOk &&
-            (carry[0] > ba.wt_cap || carry[1] > ba.zt_cap || carry[2] > ba.mc_cap ||
-             ba.w_off[ba.B] > ba.sumM_cap || ba.n_off[ba.B] > ba.sumN_cap))
+            (total[0] > ba.wt_cap || total[1] > ba.zt_cap || total[2] > ba.mc_cap ||
+             ba.w_off[B] > ba.sumM_cap || ba.n_off[B] > ba.sumN_cap))
             st = kStatusCapacity;
         ba.head[0] = st;
         ba.head[1] = st;

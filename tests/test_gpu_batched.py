@@ -133,13 +133,15 @@ def test_batched_bad_filter_is_isolated(dcr, dev):
     w, w_off, n_off = small_batch(20, 14)
     w[w_off[3] + 1] = -1.0            # filter 3: negative weight
     w[w_off[11]] = np.nan             # filter 11: NaN
+    w[w_off[16]:w_off[17]] = 0.0      # filter 16: zero total
+    bad_f = (3, 11, 16)
     r, seg, st = run_batched(dcr, dev, w, w_off, n_off, 2)
     assert st == 6
-    assert seg[3] == 6 and seg[11] == 6
-    assert np.all(seg[[b for b in range(20) if b not in (3, 11)]] == 0)
+    assert all(seg[b] == 6 for b in bad_f)
+    assert np.all(seg[[b for b in range(20) if b not in bad_f]] == 0)
     for b in range(20):
         part = r[n_off[b]:n_off[b + 1]]
-        if b in (3, 11):
+        if b in bad_f:
             assert np.all(part == -1)
         else:
             good = oracle.resample(w[w_off[b]:w_off[b + 1]], len(part), 2, b)[0]
