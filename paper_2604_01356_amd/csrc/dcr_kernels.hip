@@ -434,13 +434,16 @@ __global__ __launch_bounds__(kThreads) void k_reduce(const Tin* __restrict__ w, 
 constexpr int kScanThreads = kThreads;
 constexpr int kScanWaves = kScanThreads / 64;
 constexpr int kScanRegs = 16;   // ranges up to this length stay in registers
+constexpr int kBatchScanRegs = 4;
 
 // Per-thread inputs of a scan, loaded ahead of the computation so that the
 // loads of both scans (and of other data) are in flight together.
+template <int R = kScanRegs>
 struct ScanIn {
+    static constexpr int kRegs = R;
     int64_t a, e;
     bool in_regs;
-    double v[kScanRegs];
+    double v[R];
 };
 
 struct ScanOut {
@@ -457,20 +460,22 @@ struct ScanLds {
     double last[2];
 };
 
-__device__ __forceinline__ void scan_load(const double* __restrict__ in, int64_t n, ScanIn& si) {
+template <int R>
+__device__ __forceinline__ void scan_load(const double* __restrict__ in, int64_t n, ScanIn<R>& si) {
     const int t = threadIdx.x;
     const int64_t per = (n + kScanThreads - 1) / kScanThreads;
     si.a = (static_cast<int64_t>(t) * per < n) ? static_cast<int64_t>(t) * per : n;
     si.e = (si.a + per < n) ? si.a + per : n;
-    si.in_regs = per <= kScanRegs;
+    si.in_regs = per <= R;
     if (si.in_regs) {
 #pragma unroll
-        for (int k = 0; k < kScanRegs; ++k) si.v[k] = (si.a + k < si.e) ? in[si.a + k] : 0.0;
+        for (int k = 0; k < R; ++k) si.v[k] = (si.a + k < si.e) ? in[si.a + k] : 0.0;
     }
 }
 
 // Computes both scans; total[k] = out[n-1] of sequence k (0 if n == 0).
-__device__ void scan_pair(const ScanIn (&si)[2], const ScanOut (&so)[2], ScanLds& L,
+template <int R>
+__device__ void scan_pair(const ScanIn<R> (&si)[2], const ScanOut (&so)[2], ScanLds& L,
                           double (&total)[2], int (&bad)[2]) {
     const int t = threadIdx.x;
     const int lane64 = t & 63;
@@ -482,7 +487,7 @@ __device__ void scan_pair(const ScanIn (&si)[2], const ScanOut (&so)[2], ScanLds
         int nonfinite = 0;
         if (si[q].in_regs) {
 #pragma unroll
-            for (int k = 0; k < kScanRegs; ++k) {
+            for (int k = 0; k < R; ++k) {
                 tt = tt + si[q].v[k];   // + 0.0 past the range is exact
                 nonfinite |= !(si[q].v[k] < __builtin_huge_val());
             }
@@ -548,7 +553,7 @@ __device__ void scan_pair(const ScanIn (&si)[2], const ScanOut (&so)[2], ScanLds
         double p = 0.0;
         if (si[q].in_regs) {
 #pragma unroll
-            for (int k = 0; k < kScanRegs; ++k) {
+            for (int k = 0; k < R; ++k) {
                 if (a + k < e) {
                     p = p + si[q].v[k];
                     const double o = fmin(gamma + p, gnext);
@@ -625,10 +630,11 @@ __device__ __forceinline__ void store_uniforms(double* __restrict__ u, int64_t i
 // ---------------------------------------------------------------------------
 // k_carries: block-total scans (weights and spacings), totals and validity.
 // ---------------------------------------------------------------------------
+template <int R = kScanRegs>
 __device__ __forceinline__ void carries_body(const WArgs& wa, const ZArgs& za, const SharedArgs& sh,
                                              int32_t* dev_status, double* total_out, ScanLds& L) {
     const int t = threadIdx.x;
-    ScanIn si[2];
+    ScanIn<R> si[2];
     scan_load(wa.blk_tot, wa.nb, si[0]);
     scan_load(za.blk_tot, za.nb, si[1]);
     const ScanOut so[2] = {{wa.blk_tot, wa.nb, nullptr, wa.beta}, {za.blk_tot, za.nb, nullptr, za.beta}};
@@ -1353,7 +1359,7 @@ __device__ __forceinline__ void k_finish_body(Src w, WArgs wa, ZArgs za, SharedA
     const int64_t i0 = static_cast<int64_t>(blockIdx.x) * kUPerWG * UPQ + (t / kQuad);
     // every independent load first: the block totals of both scans and the
     // in-block spacing prefixes of this quad's draws
-    ScanIn si[2];
+    ScanIn<> si[2];
     scan_load(wa.blk_tot, wa.nb, si[0]);
     scan_load(za.blk_tot, za.nb, si[1]);
     const bool spacings = za.scheme == kSchemeMultinomial;
@@ -1739,7 +1745,10 @@ __global__ __launch_bounds__(kScanThreads) void k_carries_batched(BatchArgs ba) 
     if (ba.head[0] != kStatusOk) return;
     const int b = blockIdx.x;
     const SharedArgs sh = seg_shared(ba, b);
-    carries_body(seg_wargs(ba, b), seg_zargs(ba, b), sh, nullptr, nullptr, L);
+    // a filter's few block totals: fewer of them held in registers (the
+    // others are read again), so that more filters are resident at once;
+    // the sums are the same either way
+    carries_body<kBatchScanRegs>(seg_wargs(ba, b), seg_zargs(ba, b), sh, nullptr, nullptr, L);
     if (threadIdx.x == 0 && sh.status[0] != kStatusOk) atomicMax(ba.head + 1, kStatusBadWeights);
 }
 
