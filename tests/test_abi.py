@@ -194,3 +194,22 @@ def test_package_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(_binding, "_LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(ImportError):
         _binding.library()
+
+
+def test_binding_rejects_host_and_mistyped_tensors(lib):
+    """The Python binding checks its tensors before any call: host tensors,
+    unsupported dtypes and factors of different dtypes are refused."""
+    torch = pytest.importorskip("torch")
+    import paper_2604_01356_amd as dcr
+    w = torch.ones(100, dtype=torch.float64)            # a host tensor
+    with pytest.raises(ValueError):
+        dcr.dcr_resample(w, 10, seed=1)
+    with pytest.raises(ValueError):
+        dcr.dcr_cumulative_weights(w)
+    with pytest.raises(ValueError):
+        dcr.dcr_resample_outer(torch.ones(10), torch.ones(10), 5, seed=1)
+    with pytest.raises(TypeError):
+        dcr.precision_of(torch.ones(10, dtype=torch.int32))
+    with pytest.raises(ValueError):
+        dcr.dcr_resample_batched(w, torch.zeros(2, dtype=torch.int64),
+                                 torch.zeros(2, dtype=torch.int64), 1, sumN_max=1)
