@@ -577,9 +577,16 @@ dcr_status dcr_profile_begin(int32_t cap) {
     if (cap < 1 || g_prof.on) return DCR_ERR_INVALID_ARGUMENT;
     g_prof.ev.assign(2 * static_cast<size_t>(cap), nullptr);
     g_prof.kind.assign(cap, -1);
-    for (auto& ev : g_prof.ev)
-        if (hipEventCreateWithFlags(&ev, hipEventDisableSystemFence) != hipSuccess)
+    for (auto& ev : g_prof.ev) {
+        if (hipEventCreateWithFlags(&ev, hipEventDisableSystemFence) != hipSuccess) {
+            ev = nullptr;
+            for (auto& made : g_prof.ev)   // release what was created
+                if (made) (void)hipEventDestroy(made);
+            g_prof.ev.clear();
+            g_prof.kind.clear();
             return DCR_ERR_HIP;
+        }
+    }
     g_prof.cap = cap;
     g_prof.used = 0;
     g_prof.on = true;
