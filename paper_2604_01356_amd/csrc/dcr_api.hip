@@ -529,7 +529,11 @@ dcr_status dcr_batched_autotune(const void* w, const int64_t* w_off, const int64
         return DCR_OK;
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return DCR_ERR_HIP;
+    if (hipEventCreate(&e0) != hipSuccess) return DCR_ERR_HIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return DCR_ERR_HIP;
+    }
     dcr_status st = DCR_OK;
     float best = -1.0f;
     int32_t pick = dcr::kBatchChunkDefault;
