@@ -855,34 +855,35 @@ __device__ SubtileLoc locate_subtile(const WArgs& wa, const double* sbeta, int64
     const double* se = wa.sub_end + b * kWSubPerBlock;
     // ---- sub-tile level: first s with end(s) >= x, where
     //      end(s) = min(beta_b + sigma_{s+1}, beta_{b+1}) and end(nsub-1) = beta_{b+1};
-    //      lane qi counts the ends below x among sub-tiles 32qi .. 32qi+31 ----
+    //      the quad reads the block's 128 stored ends 64 contiguous bytes per
+    //      load (lane qi the 16-byte pieces qi, qi + 4, ...: one cache line per
+    //      quad and load, where a lane-per-quarter split touches four) and
+    //      counts those below x.  The whole row lies in the workspace; entries
+    //      past the block's last sub-tile are read but not counted. ----
     constexpr int kPerLane = kWSubPerBlock / kQuad;
-    const int s0 = kPerLane * qi;
-    double e[kPerLane];
-    if (s0 + kPerLane - 1 < nsub - 1) {
-        const f64x2* q = reinterpret_cast<const f64x2*>(se + s0);
+    double e[kPerLane];   // e[k] = end of sub-tile se_index(k)
+    {
+        const f64x2* q = reinterpret_cast<const f64x2*>(se) + qi;
 #pragma unroll
         for (int v = 0; v < kPerLane / 2; ++v) {
-            const f64x2 d = q[v];
+            const f64x2 d = q[kQuad * v];
             e[2 * v] = d.x;
             e[2 * v + 1] = d.y;
         }
-    } else {
-#pragma unroll
-        for (int k = 0; k < kPerLane; ++k) e[k] = (s0 + k < nsub - 1) ? se[s0 + k] : 0.0;
     }
+    auto se_index = [qi](int k) { return 2 * kQuad * (k >> 1) + 2 * qi + (k & 1); };
     int cnt = 0;
 #pragma unroll
     for (int k = 0; k < kPerLane; ++k)
-        cnt += (s0 + k < nsub - 1 && fmin(beta_b + e[k], beta_n) < x) ? 1 : 0;
+        cnt += (se_index(k) < nsub - 1 && fmin(beta_b + e[k], beta_n) < x) ? 1 : 0;
     const int s = quad_sum(cnt);
     L.s = s;
     // sigma_s = stored end of sub-tile s-1, taken from the lane that read it
     double sig = 0.0;
 #pragma unroll
     for (int k = 0; k < kPerLane; ++k)
-        if (s0 + k == s - 1) sig = e[k];
-    L.sigma = (s == 0) ? 0.0 : quad_bcast(sig, (s - 1) / kPerLane);
+        if (se_index(k) == s - 1) sig = e[k];
+    L.sigma = (s == 0) ? 0.0 : quad_bcast(sig, ((s - 1) % (2 * kQuad)) >> 1);
     return L;
 }
 
@@ -913,14 +914,19 @@ __device__ int64_t locate_subtile_index(const WArgs& wa, const double* sbeta, in
     const double beta_n = wa.beta[b];
     const int64_t blen = (wa.M - b * kWBlock < kWBlock) ? wa.M - b * kWBlock : kWBlock;
     const int nsub = static_cast<int>((blen + kSub - 1) / kSub);
-    const double* se = wa.sub_end + b * kWSubPerBlock;
-    constexpr int kPerLane = kWSubPerBlock / kQuad;
+    // the block's 128 stored ends, read as in locate_subtile: lane qi takes
+    // the 16-byte pieces qi, qi + 4, ..., four at a time
+    const f64x2* se = reinterpret_cast<const f64x2*>(wa.sub_end + b * kWSubPerBlock) + qi;
+    constexpr int kPieces = kWSubPerBlock / (2 * kQuad);   // per lane
     int cnt = 0;
-    for (int c8 = 0; c8 < kPerLane; c8 += 8) {
-        const int s0 = kPerLane * qi + c8;
+    for (int v4 = 0; v4 < kPieces; v4 += 4) {
 #pragma unroll
-        for (int k = 0; k < 8; ++k)
-            cnt += (s0 + k < nsub - 1 && fmin(beta_b + se[s0 + k], beta_n) < x) ? 1 : 0;
+        for (int v = v4; v < v4 + 4; ++v) {
+            const f64x2 d = se[kQuad * v];
+            const int s0 = 2 * kQuad * v + 2 * qi;
+            cnt += (s0 < nsub - 1 && fmin(beta_b + d.x, beta_n) < x) ? 1 : 0;
+            cnt += (s0 + 1 < nsub - 1 && fmin(beta_b + d.y, beta_n) < x) ? 1 : 0;
+        }
     }
     return b * kWSubPerBlock + quad_sum(cnt);
 }
@@ -1027,17 +1033,19 @@ __device__ void map_quad(Src w, const WArgs& wa, const double* sbeta, int64_t ks
     } else {
         src_chunk(w, l0, nv, (vec_ok & 1) != 0, xx);
     }
+    // the running sum is the only dependent chain: every element's end is
+    // formed and compared (independent work), and the first one reaching x
+    // is taken from a bit mask rather than by leaving the loop
     double pk = 0.0;
-    int64_t jr = l0 + nv - 1;
-    for (int k = 0; k < nv; ++k) {
+    unsigned hit = 0;
+#pragma unroll
+    for (int k = 0; k < kLane; ++k) {
         pk = pk + xx[k];
         const int64_t j = l0 + k;
         const double en = (j == jlast) ? beta_n : fmin(beta_b + (sigma + (cf + pk)), beta_n);
-        if (en >= x) {
-            jr = j;
-            break;
-        }
+        hit |= (k < nv && en >= x) ? (1u << k) : 0u;
     }
+    const int64_t jr = hit ? l0 + __builtin_ctz(hit) : l0 + nv - 1;
     r[i] = static_cast<int32_t>(jr);
 }
 
