@@ -443,6 +443,7 @@ struct ScanIn {
     static constexpr int kRegs = R;
     int64_t a, e;
     bool in_regs;
+    int per;   // elements per thread when in registers (workgroup-uniform), else 0
     double v[R];
 };
 
@@ -458,6 +459,7 @@ struct ScanLds {
     double wmax[2][kScanWaves];
     int wbad[2][kScanWaves];
     double last[2];
+    double spare[2];   // receives the unused outputs of a thread's last registers
 };
 
 template <int R>
@@ -467,9 +469,11 @@ __device__ __forceinline__ void scan_load(const double* __restrict__ in, int64_t
     si.a = (static_cast<int64_t>(t) * per < n) ? static_cast<int64_t>(t) * per : n;
     si.e = (si.a + per < n) ? si.a + per : n;
     si.in_regs = per <= R;
+    si.per = si.in_regs ? static_cast<int>(per) : 0;
     if (si.in_regs) {
 #pragma unroll
-        for (int k = 0; k < R; ++k) si.v[k] = (si.a + k < si.e) ? in[si.a + k] : 0.0;
+        for (int k = 0; k < R; ++k)
+            si.v[k] = (k < si.per && si.a + k < si.e) ? in[si.a + k] : 0.0;
     }
 }
 
@@ -481,6 +485,8 @@ __device__ void scan_pair(const ScanIn<R> (&si)[2], const ScanOut (&so)[2], Scan
     const int lane64 = t & 63;
     const int wid = t >> 6;
     double excl[2], wmx[2], wb[2];
+    // the thread's running sums, kept for the outputs, and its total
+    double pre[2][R], thr[2];
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         double tt = 0.0;
@@ -489,6 +495,7 @@ __device__ void scan_pair(const ScanIn<R> (&si)[2], const ScanOut (&so)[2], Scan
 #pragma unroll
             for (int k = 0; k < R; ++k) {
                 tt = tt + si[q].v[k];   // + 0.0 past the range is exact
+                pre[q][k] = tt;
                 nonfinite |= !(si[q].v[k] < __builtin_huge_val());
             }
         } else {
@@ -498,6 +505,7 @@ __device__ void scan_pair(const ScanIn<R> (&si)[2], const ScanOut (&so)[2], Scan
                 nonfinite |= !(x < __builtin_huge_val());
             }
         }
+        thr[q] = tt;
         const double incl = wave_incl_add(tt);
         excl[q] = wave_shift_up1(incl);
         const bool wave_bad = __builtin_amdgcn_ballot_w64(nonfinite != 0) != 0;
@@ -552,16 +560,23 @@ __device__ void scan_pair(const ScanIn<R> (&si)[2], const ScanOut (&so)[2], Scan
         const int64_t a = si[q].a, e = si[q].e, n = so[q].n;
         double p = 0.0;
         if (si[q].in_regs) {
+            // outputs from the running sums of the first pass, for the
+            // workgroup-uniform count per thread (a scalar branch); past the
+            // range they repeat the thread's total and go to a spare LDS slot,
+            // so that only the addresses depend on the range
+            const int cnt = static_cast<int>(e - a);   // 0 .. per
+            double* const dst = so[q].out_lds + a;
 #pragma unroll
             for (int k = 0; k < R; ++k) {
-                if (a + k < e) {
-                    p = p + si[q].v[k];
-                    const double o = fmin(gamma + p, gnext);
-                    if (so[q].out_lds) so[q].out_lds[a + k] = o;
-                    if (so[q].out_gl) so[q].out_gl[a + k] = o;
-                    if (a + k == n - 1) L.last[q] = o;
+                if (k < si[q].per) {
+                    const double o = fmin(gamma + pre[q][k], gnext);
+                    if (so[q].out_lds) *((k < cnt) ? dst + k : &L.spare[q]) = o;
+                    if (so[q].out_gl && k < cnt) so[q].out_gl[a + k] = o;
                 }
             }
+            // the last output is the one of the thread's total (the sums repeat
+            // it past the range)
+            if (a <= n - 1 && n - 1 < e) L.last[q] = fmin(gamma + thr[q], gnext);
         } else {
             for (int64_t j = a; j < e; ++j) {
                 p = p + so[q].in[j];
@@ -1377,11 +1392,14 @@ __device__ __forceinline__ void k_finish_body(Src w, WArgs wa, ZArgs za, SharedA
         const int64_t i = i0 + static_cast<int64_t>(k) * kUPerWG;
         zrel[k] = (spacings && i < za.N) ? za.zrel[i] : 0.0;
     }
-    const ScanOut so[2] = {{wa.blk_tot, wa.nb, sbeta, lead ? wa.beta : nullptr},
-                           {za.blk_tot, za.nb, szbeta, lead ? za.beta : nullptr}};
+    const ScanOut so[2] = {{wa.blk_tot, wa.nb, sbeta, nullptr}, {za.blk_tot, za.nb, szbeta, nullptr}};
     double tt[2];
     int bad[2];
     scan_pair(si, so, L, tt, bad);
+    if (lead) {   // publish the scans, from LDS, with coalesced stores
+        for (int64_t j = t; j < wa.nb; j += kThreads) wa.beta[j] = sbeta[j];
+        for (int64_t j = t; j < za.nb; j += kThreads) za.beta[j] = szbeta[j];
+    }
     const double tot = tt[0], ztot = tt[1];
     const int status =
         (bad[0] || !(tot > 0.0) || !(tot < __builtin_huge_val())) ? kStatusBadWeights : kStatusOk;
