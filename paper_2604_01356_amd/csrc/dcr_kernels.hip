@@ -957,15 +957,19 @@ __device__ void map_quad(Src w, const WArgs& wa, const double* sbeta, int64_t ks
     const int64_t sub0 = blk0 + static_cast<int64_t>(s) * kSub;
     const int slen = static_cast<int>((jlast - sub0 + 1 < kSub) ? jlast - sub0 + 1 : kSub);
     const int nl = (slen + kLane - 1) / kLane;
-    // ---- lane-chunk level: lane qi sums chunks 4qi .. 4qi+3 ----
+    // ---- lane-chunk level: lane qi sums chunks qi, qi + 4, qi + 8, qi + 12,
+    //      so that a load of the quad spans 64 contiguous bytes per chunk row
+    //      (two cache lines of binary32 weights where consecutive chunks per
+    //      lane span four) ----
     constexpr int kChunks = kRowLanes / kQuad;
-    double tl[kChunks];
+    static_assert(kQuad == 4 && kChunks == 4, "four lanes per quad, four chunks per lane");
+    double tl[kChunks];   // tl[q] = total of chunk qi + 4q
     const bool full_sub = (slen == kSub) && (vec_ok & 1);
     RawChunk<Elem> rc[kChunks];
     if (full_sub) {
 #pragma unroll
         for (int q = 0; q < kChunks; ++q)
-            rc[q] = src_raw(w, sub0 + (kChunks * qi + q) * kLane);
+            rc[q] = src_raw(w, sub0 + (qi + kQuad * q) * kLane);
 #pragma unroll
         for (int q = 0; q < kChunks; ++q) {
             Elem mn = static_cast<Elem>(0);
@@ -974,65 +978,52 @@ __device__ void map_quad(Src w, const WArgs& wa, const double* sbeta, int64_t ks
     } else {
 #pragma unroll
         for (int q = 0; q < kChunks; ++q) {
-            const int l = kChunks * qi + q;
+            const int l = qi + kQuad * q;
             const int nv = (l < nl) ? ((slen - l * kLane < kLane) ? slen - l * kLane : kLane) : 0;
             double xx[kLane];
             src_chunk(w, sub0 + l * kLane, nv, (vec_ok & 1) != 0, xx);
             tl[q] = chunk_sum(xx);
         }
     }
-    // left-to-right chunk bases c_l across the quad: lane q continues from
-    // the end of lane q-1's four chunks, so the sums are the same additions in
-    // the same order as one lane running over all 16
+    // left-to-right chunk starts c_l: c_{l+1} = c_l + (total of chunk l),
+    // added by the lane that holds chunk l and passed to the whole quad, so
+    // the sums are the same additions in the same order as one lane running
+    // over all 16 chunks; cb[q] = start of chunk qi + 4q
     const bool last_sub = (s == nsub - 1);   // its last chunk ends at beta_{b+1}
-    double base = 0.0;
+    double cb[kChunks];
     {
-        static_assert(kQuad == 4, "four lanes per quad");
-        double start = 0.0;   // start of lane k's first chunk, k = 0, 1, 2, 3
-        auto lane_end = [&](double from) {
-            double run = from;
+        double run = 0.0;   // c_l, the same in every lane of the quad
 #pragma unroll
-            for (int q = 0; q < kChunks; ++q) run = run + tl[q];
-            return run;
-        };
-        base = (qi == 0) ? start : base;
-        start = dpp_f64<kDppQuadBcast(0)>(lane_end(start));
-        base = (qi == 1) ? start : base;
-        start = dpp_f64<kDppQuadBcast(1)>(lane_end(start));
-        base = (qi == 2) ? start : base;
-        start = dpp_f64<kDppQuadBcast(2)>(lane_end(start));
-        base = (qi == 3) ? start : base;
-    }
-    // each lane looks for the first of its chunks ending at >= x; the first
-    // lane of the quad that finds one holds the first such chunk (the ends
-    // are non-decreasing) and takes the element level
-    int lf = -1;
-    double c = base, cf = 0.0, cprev = base;
-#pragma unroll
-    for (int q = 0; q < kChunks; ++q) {
-        const int l = kChunks * qi + q;
-        if (l < nl && lf < 0) {
-            const double cn = c + tl[q];
-            const double en =
-                (last_sub && l == nl - 1) ? beta_n : fmin(beta_b + (sigma + cn), beta_n);
-            if (en >= x) {
-                lf = l;
-                cf = c;
-            }
-            cprev = c;
-            c = cn;
+        for (int q = 0; q < kChunks; ++q) {
+            cb[q] = (qi == 0) ? run : 0.0;
+            run = dpp_f64<kDppQuadBcast(0)>(run + tl[q]);
+            cb[q] = (qi == 1) ? run : cb[q];
+            run = dpp_f64<kDppQuadBcast(1)>(run + tl[q]);
+            cb[q] = (qi == 2) ? run : cb[q];
+            run = dpp_f64<kDppQuadBcast(2)>(run + tl[q]);
+            cb[q] = (qi == 3) ? run : cb[q];
+            run = dpp_f64<kDppQuadBcast(3)>(run + tl[q]);
         }
     }
-    const unsigned qmask =
-        static_cast<unsigned>(__ballot(lf >= 0) >> ((threadIdx.x & 63) & ~(kQuad - 1))) & 0xFu;
-    int owner;
-    if (qmask != 0) {
-        owner = __builtin_ctz(qmask);
-    } else {  // unreachable: the sub-tile's end is >= x by the search above
-        owner = (nl - 1) / kChunks;
-        lf = nl - 1;
-        cf = cprev;
+    // each lane finds the first of its chunks ending at >= x; the quad's
+    // first such chunk (the ends are non-decreasing) is the smallest of these
+    // and its lane takes the element level
+    constexpr int kNone = kRowLanes;
+    int lmine = kNone;
+#pragma unroll
+    for (int q = kChunks - 1; q >= 0; --q) {
+        const int l = qi + kQuad * q;
+        const double en =
+            (last_sub && l == nl - 1) ? beta_n : fmin(beta_b + (sigma + (cb[q] + tl[q])), beta_n);
+        lmine = (l < nl && en >= x) ? l : lmine;
     }
+    int lf = min(lmine, dpp_i32<kDppQuadSwap1>(lmine));
+    lf = min(lf, dpp_i32<kDppQuadSwap2>(lf));
+    if (lf == kNone) lf = nl - 1;   // unreachable: the sub-tile's end is >= x by the search above
+    const int owner = lf % kQuad;
+    double cf = cb[0];   // start of chunk lf, in its lane
+#pragma unroll
+    for (int q = 1; q < kChunks; ++q) cf = (q == lf / kQuad) ? cb[q] : cf;
     if (qi != owner) return;
     // ---- element level, by the lane that summed chunk lf ----
     const int64_t l0 = sub0 + static_cast<int64_t>(lf) * kLane;
@@ -1042,7 +1033,7 @@ __device__ void map_quad(Src w, const WArgs& wa, const double* sbeta, int64_t ks
         RawChunk<Elem> sel = rc[0];
 #pragma unroll
         for (int q = 1; q < kChunks; ++q)
-            if (q == lf % kChunks) sel = rc[q];
+            if (q == lf / kQuad) sel = rc[q];
 #pragma unroll
         for (int k = 0; k < kLane; ++k) xx[k] = sel.at(k);
     } else {
