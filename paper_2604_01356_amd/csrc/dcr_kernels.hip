@@ -435,6 +435,7 @@ constexpr int kScanThreads = kThreads;
 constexpr int kScanWaves = kScanThreads / 64;
 constexpr int kScanRegs = 16;   // ranges up to this length stay in registers
 constexpr int kBatchScanRegs = 4;
+constexpr int kScanBatch = 16;  // loads in flight per thread when the ranges are longer
 
 // Per-thread inputs of a scan, loaded ahead of the computation so that the
 // loads of both scans (and of other data) are in flight together.
@@ -498,11 +499,17 @@ __device__ void scan_pair(const ScanIn<R> (&si)[2], const ScanOut (&so)[2], Scan
                 pre[q][k] = tt;
                 nonfinite |= !(si[q].v[k] < __builtin_huge_val());
             }
-        } else {
-            for (int64_t j = si[q].a; j < si[q].e; ++j) {
-                const double x = so[q].in[j];
-                tt = tt + x;
-                nonfinite |= !(x < __builtin_huge_val());
+        } else {   // batches of loads in flight together, then their sums
+            for (int64_t j0 = si[q].a; j0 < si[q].e; j0 += kScanBatch) {
+                double x[kScanBatch];
+#pragma unroll
+                for (int k = 0; k < kScanBatch; ++k)
+                    x[k] = (j0 + k < si[q].e) ? so[q].in[j0 + k] : 0.0;
+#pragma unroll
+                for (int k = 0; k < kScanBatch; ++k) {
+                    tt = tt + x[k];   // + 0.0 past the range is exact
+                    nonfinite |= !(x[k] < __builtin_huge_val());
+                }
             }
         }
         thr[q] = tt;
@@ -578,12 +585,21 @@ __device__ void scan_pair(const ScanIn<R> (&si)[2], const ScanOut (&so)[2], Scan
             // it past the range)
             if (a <= n - 1 && n - 1 < e) L.last[q] = fmin(gamma + thr[q], gnext);
         } else {
-            for (int64_t j = a; j < e; ++j) {
-                p = p + so[q].in[j];
-                const double o = fmin(gamma + p, gnext);
-                if (so[q].out_lds) so[q].out_lds[j] = o;
-                if (so[q].out_gl) so[q].out_gl[j] = o;
-                if (j == n - 1) L.last[q] = o;
+            for (int64_t j0 = a; j0 < e; j0 += kScanBatch) {
+                double x[kScanBatch];
+#pragma unroll
+                for (int k = 0; k < kScanBatch; ++k) x[k] = (j0 + k < e) ? so[q].in[j0 + k] : 0.0;
+#pragma unroll
+                for (int k = 0; k < kScanBatch; ++k) {
+                    const int64_t j = j0 + k;
+                    if (j < e) {
+                        p = p + x[k];
+                        const double o = fmin(gamma + p, gnext);
+                        if (so[q].out_lds) so[q].out_lds[j] = o;
+                        if (so[q].out_gl) so[q].out_gl[j] = o;
+                        if (j == n - 1) L.last[q] = o;
+                    }
+                }
             }
         }
         if (n == 0 && t == 0) L.last[q] = 0.0;
