@@ -530,7 +530,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build measures one MI355X only; multi-GPU runs (--gpus > 1) "
+        print("bench.py: measures one MI355X only; multi-GPU runs (--gpus > 1) "
               "are not supported", file=sys.stderr)
         sys.exit(2)
 
