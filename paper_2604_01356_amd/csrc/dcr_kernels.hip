@@ -572,7 +572,7 @@ __device__ void scan_pair(const ScanIn<R> (&si)[2], const ScanOut (&so)[2], Scan
             // range they repeat the thread's total and go to a spare LDS slot,
             // so that only the addresses depend on the range
             const int cnt = static_cast<int>(e - a);   // 0 .. per
-            double* const dst = so[q].out_lds + a;
+            double* const dst = so[q].out_lds ? so[q].out_lds + a : nullptr;
 #pragma unroll
             for (int k = 0; k < R; ++k) {
                 if (k < si[q].per) {
