@@ -189,6 +189,19 @@ def test_many_blocks_sampled_index(dev, dcr):
     check_against_oracle(out, w, 5000, 4, 1, DU_FP32, 2.0**-40)
 
 
+@pytest.mark.parametrize("N", [3000, 262143])
+def test_largest_single_launch_finish(dev, dcr, N):
+    """The largest problem the single finishing launch takes: 4096 weight blocks
+    (every scan thread holds 16 block totals in registers, the last block
+    ragged) and, at N = 2^18 - 1, 64 spacing blocks with four draws per quad."""
+    M = (1 << 27) - 7
+    rng = np.random.default_rng(123)
+    w = np.exp(rng.normal(0, 3, M)).astype(np.float32)
+    print(f"  largest finish: M={M} N={N}", flush=True)
+    out = run_case(dcr, dev, w, N, seed=6, stream=2)
+    check_against_oracle(out, w, N, 6, 2, DU_FP32, 2.0**-40)
+
+
 @pytest.mark.parametrize("which", ["sparse", "equal"])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_full_size(dev, dcr, which, dtype):
