@@ -40,9 +40,10 @@ def _factors(Na, P, seed, dtype):
     return a, b
 
 
-# (Na, P, N): the EnGMF step shape (one finishing launch), a large sparse case
-# (carries + map), a dense case (merge) and ragged sizes
-# and the large EnGMF-shaped step timed beside the main measurement
+# (Na, P, N): the EnGMF step shape and a larger sparse case (both in the single
+# finishing launch), a dense case (merge), ragged sizes, and the large
+# EnGMF-shaped step timed beside the main measurement.  The outer twin of the
+# sparse map after a separate carry scan is covered in test_gpu_map_fused.py.
 CASES = [(2000, 64, 2000), (20000, 1000, 3000), (3000, 7, 20000), (1, 1, 5), (977, 33, 1),
          (65536, 256, 65536)]
 

@@ -12,7 +12,8 @@ from scipy import stats
 
 import oracle
 import workloads
-from parity_util import assert_monotone_unit, classify_mismatches
+from gpu_util import DU_FP32, check_against_oracle, run_case, to_dev
+from parity_util import assert_monotone_unit
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -34,60 +35,12 @@ def dcr():
 
 
 def _t(a, dev):
-    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    return to_dev(a, dev)
 
-
-def run_case(dcr, dev, w, N, seed, stream):
-    M = w.shape[0]
-    wt = _t(w, dev)
-    W = torch.empty(M, dtype=torch.float64, device=dev)
-    u = torch.empty(max(N, 1), dtype=torch.float64, device=dev)
-    st = torch.full((1,), -1, dtype=torch.int32, device=dev)
-    r = dcr.dcr_resample(wt, N, seed, stream, W_out=W, u_out=u, dev_status=st)
-    r_plain = dcr.dcr_resample(wt, N, seed, stream)        # W and u never written
-    W1 = dcr.dcr_cumulative_weights(wt)
-    prec = dcr.precision_of(wt)
-    u2 = dcr.dcr_sorted_uniforms(N, seed, stream, precision=prec, device=dev)
-    r3 = dcr.dcr_inverse_cmf(W1, u2)
-    torch.cuda.synchronize()
-    assert int(st.item()) == 0
-    out = dict(r=r.cpu().numpy(), W=W.cpu().numpy(), u=u[:N].cpu().numpy(),
-               r_plain=r_plain.cpu().numpy(), W1=W1.cpu().numpy(), u2=u2.cpu().numpy(),
-               r3=r3.cpu().numpy())
-    # fused == staged, bit for bit
-    assert np.array_equal(out["r"], out["r_plain"])
-    assert np.array_equal(out["W"], out["W1"])
-    assert np.array_equal(out["u"], out["u2"])
-    assert np.array_equal(out["r"], out["r3"])
-    return out
-
-
-def check_against_oracle(out, w, N, seed, stream, du_cap, dW_cap):
-    r_o, W_o, u_o = oracle.resample(w, N, seed, stream)
-    assert_monotone_unit(out["W"])
-    if N:
-        assert np.all(np.diff(out["u"]) >= 0) and out["u"][0] > 0 and out["u"][-1] <= 1
-        assert np.all(np.diff(out["r"]) >= 0)
-        # the index map is exact on the GPU's own W and u
-        r_exact, _ = oracle.dac(out["W"], out["u"])
-        assert np.array_equal(out["r"], r_exact)
-    dW = np.max(np.abs(out["W"] - W_o))
-    du = np.max(np.abs(out["u"] - u_o)) if N else 0.0
-    assert dW <= dW_cap, dW
-    assert du <= du_cap, du
-    n_mis, bad = classify_mismatches(out["r"], r_o, out["u"], u_o, out["W"], W_o)
-    assert not bad, f"{len(bad)} mismatches away from bin edges, e.g. {bad[:5]}"
-    print(f"  M={len(w)} N={N} dW={dW:.2e} du={du:.2e} bin-edge mismatches={n_mis}", flush=True)
-    return n_mis
-
-
-# binary32 spacings: the two logf implementations are each within 1 ulp, so
-# |dz_i| <= 2^-22 z_i, |dZ_i| <= 2^-22 Z_i and |du_i| <= 2^-21 u_i.
-DU_FP32 = 2.0**-21
 
 # (M, N): ragged edges of lanes, sub-tiles, blocks and spacing blocks; two
 # sparse cases with two and four draws per quad in the finishing launch; the
-# last two take the multi-launch path (N + 1 > 2^18 spacings)
+# last two are dense (N >= M/4: the windowed merge) with N + 1 >= 2^18
 RAGGED = [(1, 5), (3, 1), (5, 0), (100, 1000), (32769, 4097), (65537, 3), (40000, 4095),
           (300001, 8191), (4194307, 40001), (8388617, 150001), (100003, 262143),
           (70001, 300000)]
@@ -179,16 +132,6 @@ def test_dense_with_light_gap(dev, dcr, dtype):
     check_against_oracle(out, w, N, 8, 0, 1e-12 if dtype == np.float64 else DU_FP32, 2.0**-40)
 
 
-def test_many_blocks_sampled_index(dev, dcr):
-    """More than 4096 weight blocks (M > 2^27): the map keeps every second block
-    end in LDS and finishes the block search in memory."""
-    M = (1 << 27) + 12345
-    rng = np.random.default_rng(99)
-    w = np.exp(rng.normal(0, 4, M)).astype(np.float32)
-    out = run_case(dcr, dev, w, 5000, seed=4, stream=1)
-    check_against_oracle(out, w, 5000, 4, 1, DU_FP32, 2.0**-40)
-
-
 @pytest.mark.parametrize("N", [3000, 262143])
 def test_largest_single_launch_finish(dev, dcr, N):
     """The largest problem the single finishing launch takes: 4096 weight blocks
@@ -198,7 +141,7 @@ def test_largest_single_launch_finish(dev, dcr, N):
     rng = np.random.default_rng(123)
     w = np.exp(rng.normal(0, 3, M)).astype(np.float32)
     print(f"  largest finish: M={M} N={N}", flush=True)
-    out = run_case(dcr, dev, w, N, seed=6, stream=2)
+    out = run_case(dcr, dev, w, N, seed=6, stream=2, expect="finish")
     check_against_oracle(out, w, N, 6, 2, DU_FP32, 2.0**-40)
 
 
