@@ -210,21 +210,30 @@ void dcro_inverse_cmf_count(const double* W, int64_t M, const double* u, int64_t
 }
 
 /* ------------------------------------------------------------------------- */
-/* Sec. II, Alg. 2: modified binary search over Z[a..b] (inclusive) for X.     */
-/* Returns the first index m in [a, b] with Z_m >= X, or b if there is none.  */
+/* Sec. II, Alg. 2 (the search the samplers share): over the inclusive range  */
+/* Z[a..b] of a non-decreasing list, the first index m with Z_m >= X, or b    */
+/* when no index before b qualifies (the clamp of reading R5).                */
+/*                                                                           */
+/* Written from that definition: the indices in [a, b) whose value is below X */
+/* form a prefix of the range (Z is non-decreasing), so the answer is a plus  */
+/* the length of that prefix.  The length is assembled from its binary digits,*/
+/* largest first: a candidate step s is kept when the element s past the      */
+/* prefix found so far is still below X.  Each probe is one comparison, which */
+/* ncmp counts (about log2 of the range length per search, as Table I states  */
+/* for the binary sampler).                                                   */
 /* ------------------------------------------------------------------------- */
 int64_t dcro_binary_search(const double* Z, int64_t a, int64_t b, double X, int64_t* ncmp)
 {
-    int64_t m = (a + b) / 2;
-    while (a != b) {
+    const int64_t n = b - a; /* candidates a .. b-1; b is the fall-back */
+    int64_t top = 1;
+    while (top <= n / 2) top *= 2;
+    int64_t below = 0; /* length of the prefix of [a, b) known to lie below X */
+    for (int64_t s = (n > 0) ? top : 0; s > 0; s /= 2) {
+        if (below + s > n) continue;
         if (ncmp) ++*ncmp;
-        if (Z[m] < X)
-            a = m + 1;
-        else
-            b = m;
-        m = (a + b) / 2;
+        if (Z[a + below + s - 1] < X) below += s;
     }
-    return b;
+    return a + below;
 }
 
 /* Sec. II, Alg. 3 with the uniforms supplied: one full-range search each. */
@@ -252,58 +261,62 @@ void dcro_ccf(const double* W, int64_t M, const double* u, int64_t N, int32_t* r
 }
 
 /* ------------------------------------------------------------------------- */
-/* Sec. III, Alg. 5: divide and conquer.  Split the sorted uniforms at their   */
-/* lower middle, locate it in the current range of W with Alg. 2, recurse on   */
-/* the left part with W[aW..mW] and on the right part with W[mW..bW].  Base    */
-/* cases: one uniform -> Alg. 2; one weight -> every uniform takes it.         */
-/* A trace of (depth, uniform index, weight index) is kept for every located  */
-/* uniform if requested.                                                       */
+/* Sec. III, Alg. 5: divide and conquer.  The sorted uniforms are located by  */
+/* narrowing, for a contiguous run of them, the stretch of W their answers    */
+/* must lie in.  A pending task is a run of uniforms U[iu0..iu1] together with */
+/* a stretch W[jw0..jw1] known to contain every answer of the run.  Handling a */
+/* task: if its stretch is a single bin, that bin is every answer; otherwise  */
+/* its middle uniform (the lower middle of an even run, reading R11) is       */
+/* located in the stretch with the search above, and the uniforms before it   */
+/* become a task whose stretch ends at that answer while those after it       */
+/* become a task whose stretch starts there (the uniforms are sorted, so      */
+/* neither side can leave its part).  Tasks are handled in the order they are */
+/* made (a first-in first-out list), so every depth of the splitting is done  */
+/* before the next; the optional trace lists each located uniform as          */
+/* (depth, uniform index, weight index) in that order.                         */
 /* ------------------------------------------------------------------------- */
 typedef struct {
-    const double* U;
-    const double* W;
-    int32_t* r;
-    int64_t* ncmp;
-    int64_t* trace; /* triples; may be NULL */
-    int64_t trace_cap;
-    int64_t trace_len;
-} dac_ctx;
-
-static void dac_record(dac_ctx* c, int64_t depth, int64_t iu, int64_t jw)
-{
-    if (!c->trace || c->trace_len >= c->trace_cap) return;
-    c->trace[3 * c->trace_len + 0] = depth;
-    c->trace[3 * c->trace_len + 1] = iu;
-    c->trace[3 * c->trace_len + 2] = jw;
-    c->trace_len++;
-}
-
-static void dac_rec(dac_ctx* c, int64_t aU, int64_t bU, int64_t aW, int64_t bW, int64_t depth)
-{
-    if (aU == bU) {
-        int64_t m = dcro_binary_search(c->W, aW, bW, c->U[aU], c->ncmp);
-        c->r[aU] = (int32_t)m;
-        dac_record(c, depth, aU, m);
-    } else if (aW == bW) {
-        for (int64_t i = aU; i <= bU; ++i) c->r[i] = (int32_t)aW;
-    } else {
-        int64_t mU = (aU + bU) / 2;
-        int64_t mW = dcro_binary_search(c->W, aW, bW, c->U[mU], c->ncmp);
-        c->r[mU] = (int32_t)mW;
-        dac_record(c, depth, mU, mW);
-        if (mU > aU) dac_rec(c, aU, mU - 1, aW, mW, depth + 1);
-        if (mU < bU) dac_rec(c, mU + 1, bU, mW, bW, depth + 1);
-    }
-}
+    int64_t iu0, iu1, jw0, jw1, depth;
+} dac_task;
 
 /* Returns the trace length written (0 if no trace buffer). */
 int64_t dcro_dac(const double* W, int64_t M, const double* u, int64_t N, int32_t* r,
                  int64_t* ncmp, int64_t* trace, int64_t trace_cap)
 {
     if (N <= 0 || M <= 0) return 0;
-    dac_ctx c = {u, W, r, ncmp, trace, trace_cap, 0};
-    dac_rec(&c, 0, N - 1, 0, M - 1, 0);
-    return c.trace_len;
+    /* every task either settles all its uniforms or locates one and makes at
+     * most two new tasks, so at most 2N + 1 tasks are ever made */
+    dac_task* list = (dac_task*)malloc(sizeof(dac_task) * (size_t)(2 * N + 1));
+    if (!list) return 0;
+    int64_t made = 0, next = 0, traced = 0;
+    dac_task first = {0, N - 1, 0, M - 1, 0};
+    list[made++] = first;
+    while (next < made) {
+        const dac_task t = list[next++];
+        if (t.jw0 == t.jw1) {
+            for (int64_t i = t.iu0; i <= t.iu1; ++i) r[i] = (int32_t)t.jw0;
+            continue;
+        }
+        const int64_t mid = t.iu0 + (t.iu1 - t.iu0) / 2;
+        const int64_t at = dcro_binary_search(W, t.jw0, t.jw1, u[mid], ncmp);
+        r[mid] = (int32_t)at;
+        if (trace && traced < trace_cap) {
+            trace[3 * traced + 0] = t.depth;
+            trace[3 * traced + 1] = mid;
+            trace[3 * traced + 2] = at;
+            ++traced;
+        }
+        if (mid > t.iu0) {
+            dac_task left = {t.iu0, mid - 1, t.jw0, at, t.depth + 1};
+            list[made++] = left;
+        }
+        if (mid < t.iu1) {
+            dac_task right = {mid + 1, t.iu1, at, t.jw1, t.depth + 1};
+            list[made++] = right;
+        }
+    }
+    free(list);
+    return traced;
 }
 
 /* ------------------------------------------------------------------------- */
