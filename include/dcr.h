@@ -226,6 +226,30 @@ dcr_status dcr_batched_autotune(const void* w, const int64_t* w_off, const int64
                                 const char* cache_path, int32_t* best_chunk, float* best_ms,
                                 hipStream_t stream);
 
+/* Allocation-free end to end, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): dcr_resample_scheme without the workspace argument.  Its scratch
+ * space is a static device array of DCR_NOALLOC_SCRATCH_BYTES held by every
+ * GPU the library runs on until the process ends; the call itself allocates
+ * nothing.  The caller still owns w, r and the optional W_opt, u_opt and
+ * dev_status, with the meaning of dcr_resample_scheme, and the results equal
+ * that call's bit for bit.
+ *   Limit: the workspace dcr_workspace_bytes(M, N, p) would need must fit the
+ *   array (for example M = 2^27 with N = 2^20, or M = N = 2^21); otherwise
+ *   DCR_ERR_CAPACITY_EXCEEDED is returned before anything is enqueued.
+ *   Sharing: every call on one GPU uses that GPU's one array, so calls that
+ *   overlap on a GPU (concurrent streams, or threads) race and must be
+ *   serialised by the caller; calls in order on one stream are safe.  Nothing
+ *   in the array needs to start at zero: a call writes every word it reads.
+ * Errors: those of dcr_resample_scheme (except the workspace ones), plus
+ * DCR_ERR_CAPACITY_EXCEEDED, and DCR_ERR_HIP if the array's device address
+ * cannot be obtained on the current device. */
+#define DCR_NOALLOC_SCRATCH_BYTES (32u << 20)
+dcr_status dcr_resample_noalloc(const void* w, int64_t M, int64_t N, uint64_t seed,
+                                uint64_t stream_id, dcr_precision p, dcr_scheme scheme,
+                                int32_t* r, double* W_opt, double* u_opt, int32_t* dev_status,
+                                hipStream_t stream);
+
 /* Kernel timing for measurement (not part of the sampling contract).
  * dcr_profile_begin(cap) creates HIP events for up to `cap` kernel launches;
  * every later launch records its own start and end into the next pair

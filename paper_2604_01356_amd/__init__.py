@@ -22,6 +22,7 @@ from ._binding import (  # noqa: F401
     dcr_resample,
     dcr_resample_batched,
     dcr_resample_batched_ex,
+    dcr_resample_noalloc,
     dcr_resample_outer,
     dcr_resample_scheme,
     dcr_scheme_uniforms,

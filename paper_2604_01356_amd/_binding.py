@@ -80,6 +80,9 @@ def library():
     lib.dcr_resample_outer.restype = ctypes.c_int
     lib.dcr_scheme_uniforms.argtypes = [i64, u64, u64, ctypes.c_int, P, P]
     lib.dcr_scheme_uniforms.restype = ctypes.c_int
+    lib.dcr_resample_noalloc.argtypes = [P, i64, i64, u64, u64, ctypes.c_int, ctypes.c_int, P, P,
+                                         P, P, P]
+    lib.dcr_resample_noalloc.restype = ctypes.c_int
     lib.dcr_profile_begin.argtypes = [i32]
     lib.dcr_profile_begin.restype = ctypes.c_int
     lib.dcr_profile_end.argtypes = [i32, P, P]
@@ -286,6 +289,31 @@ def dcr_resample(w, N: int, seed: int, stream_id: int = 0, r=None, W_out=None, u
     _check("dcr_resample", library().dcr_resample(
         _ptr(w), M, N, int(seed), int(stream_id), p, _ptr(r), _ptr(W_out), _ptr(u_out),
         _ptr(dev_status), _ptr(ws), ws.numel(), _stream(w.device)))
+    return r[:N]
+
+
+def dcr_resample_noalloc(w, N: int, seed: int, stream_id: int = 0,
+                         scheme: int = DCR_MULTINOMIAL, r=None, W_out=None, u_out=None,
+                         dev_status=None):
+    """dcr_resample_scheme with no workspace argument: the library's static
+    scratch array of the current device serves instead (the C call allocates
+    nothing; a caller that cannot allocate passes r)."""
+    import torch
+    _dev_tensor(w, "w")
+    M = w.numel()
+    p = precision_of(w)
+    N = int(N)
+    if r is None:
+        r = torch.empty(max(N, 1), dtype=torch.int32, device=w.device)
+    _dev_tensor(r, "r", torch.int32, N)
+    _dev_tensor(W_out, "W_out", torch.float64, M)
+    _dev_tensor(u_out, "u_out", torch.float64, N)
+    _dev_tensor(dev_status, "dev_status", torch.int32, 1)
+    with torch.cuda.device(w.device):
+        code = library().dcr_resample_noalloc(
+            _ptr(w), M, N, int(seed), int(stream_id), p, int(scheme), _ptr(r), _ptr(W_out),
+            _ptr(u_out), _ptr(dev_status), _stream(w.device))
+    _check("dcr_resample_noalloc", code)
     return r[:N]
 
 

@@ -1,10 +1,12 @@
 // dcr_api.hip -- host side of the libdcr C ABI (declared in include/dcr.h):
 // argument validation, workspace layout and kernel enqueueing.  Nothing here
-// allocates device memory; scratch space is the caller's workspace.
+// allocates device memory; scratch space is the caller's workspace, or for
+// dcr_resample_noalloc a static device array.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
 #include <cstdio>
+#include <mutex>
 #include <vector>
 
 #include "dcr.h"
@@ -635,3 +637,59 @@ const char* dcr_profile_kind_name(int32_t kind) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// dcr_resample_noalloc: the end-to-end call with its scratch space in a static
+// device array instead of a caller's workspace, for callers that cannot
+// allocate.  Every GPU the library runs on holds its own copy of `scratch`
+// (DCR_NOALLOC_SCRATCH_BYTES) until the process ends.  On the host, `scratch`
+// names a host-side stand-in, never the device memory: the device address is
+// taken once per device with hipGetSymbolAddress and only that address is
+// handed to the kernels.  No scratch word is read before the call has written
+// it, so the array needs no clearing between calls.
+// ---------------------------------------------------------------------------
+namespace {
+
+static __device__ __align__(256) unsigned char scratch[DCR_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 256;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device, taken on its first
+// use there.
+dcr_status scratch_for_current_device(void** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return DCR_ERR_HIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr)
+            return DCR_ERR_HIP;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return DCR_OK;
+}
+
+}  // namespace
+
+extern "C" dcr_status dcr_resample_noalloc(const void* w, int64_t M, int64_t N, uint64_t seed,
+                                           uint64_t stream_id, dcr_precision p,
+                                           dcr_scheme scheme, int32_t* r, double* W_opt,
+                                           double* u_opt, int32_t* dev_status,
+                                           hipStream_t stream) {
+    // every host-visible error is reported before the first HIP call
+    if (!w || M < 1 || M > kMaxM || N < 0 || N > kMaxN || (N > 0 && !r))
+        return DCR_ERR_INVALID_ARGUMENT;
+    if (!valid_prec(p) || !valid_scheme(scheme)) return DCR_ERR_UNSUPPORTED;
+    if (make_layout(M, N, scheme).bytes > DCR_NOALLOC_SCRATCH_BYTES)
+        return DCR_ERR_CAPACITY_EXCEEDED;
+    void* ws = nullptr;
+    const dcr_status st = scratch_for_current_device(&ws);
+    if (st != DCR_OK) return st;
+    dcr::WSource src;
+    src.w = w;
+    return resample_from(src, M, N, seed, stream_id, p, scheme, r, W_opt, u_opt, dev_status, ws,
+                         DCR_NOALLOC_SCRATCH_BYTES, stream);
+}

@@ -180,6 +180,25 @@ def test_host_validation_outer(lib):
     assert f(FAKE, 10, FAKE, 10, 100, 1, 0, 0, 0, FAKE, None, None, None, FAKE, 16, None) == 3
 
 
+def test_host_validation_noalloc(lib):
+    """The allocation-free call reports every host-visible error, the size
+    check against its static scratch array included, before any HIP call."""
+    f = lib.dcr_resample_noalloc
+    assert f(None, 1000, 100, 1, 0, 0, 0, FAKE, None, None, None, None) == 1
+    assert f(FAKE, 0, 100, 1, 0, 0, 0, FAKE, None, None, None, None) == 1
+    assert f(FAKE, 1000, -1, 1, 0, 0, 0, FAKE, None, None, None, None) == 1
+    assert f(FAKE, 1000, 100, 1, 0, 0, 0, None, None, None, None, None) == 1
+    assert f(FAKE, 1000, 100, 1, 0, 5, 0, FAKE, None, None, None, None) == 2
+    assert f(FAKE, 1000, 100, 1, 0, 0, 4, FAKE, None, None, None, None) == 2
+    # more spacing blocks, or more weight blocks, than the 32 MiB array holds
+    assert f(FAKE, 1000, 1 << 23, 1, 0, 0, 0, FAKE, None, None, None, None) == 4
+    assert f(FAKE, (1 << 31) - 1, 10, 1, 0, 1, 0, FAKE, None, None, None, None) == 4
+    # the stratified scheme has no spacing side: the same N fits
+    n = ctypes.c_size_t(0)
+    assert lib.dcr_workspace_bytes(1 << 20, 1 << 22, 0, ctypes.byref(n)) == 0
+    assert n.value > (32 << 20)
+
+
 def test_profile_api_host(lib):
     assert lib.dcr_profile_kind_count() >= 5
     names = [lib.dcr_profile_kind_name(k).decode() for k in range(lib.dcr_profile_kind_count())]
