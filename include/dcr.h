@@ -146,6 +146,8 @@ dcr_status dcr_batched_workspace_bytes(int32_t B, int64_t sumM_max, int64_t sumN
  *            may start at any element (no alignment needed).
  *   w_off    [B+1] int64 DEVICE array, non-decreasing, w_off[0] == 0,
  *            1 <= M_b = w_off[b+1] - w_off[b] <= 2^31 - 1, w_off[B] <= sumM_max.
+ *            The device checks the offsets against sumM_max only, so w must
+ *            hold at least sumM_max weights (the Python binding checks this).
  *   n_off    [B+1] int64 DEVICE array, n_off[0] == 0,
  *            0 <= N_b = n_off[b+1] - n_off[b] <= 2^31 - 2, n_off[B] <= sumN_max.
  *   r        [n_off[B]] int32 out: indices local to each filter (0..M_b-1),

@@ -335,6 +335,10 @@ def _batched_args(w, w_off, n_off, sumM_max, sumN_max, r, seg_status, dev_status
         raise ValueError("w_off and n_off must have the same length")
     p = precision_of(w)
     sumM = int(w.numel() if sumM_max is None else sumM_max)
+    if sumM > w.numel():
+        # the device checks the offsets against sumM only: a bound beyond the
+        # weights would let them run past the array
+        raise ValueError(f"sumM_max = {sumM} exceeds the {w.numel()} weights of w")
     if r is None:
         if sumN_max is None:
             raise ValueError("give r or sumN_max")
@@ -381,28 +385,10 @@ def dcr_resample_batched(w, w_off, n_off, seed: int, sumM_max: int | None = None
                          ws=None):
     """B filters in one call; w_off / n_off are int64 device tensors of B+1
     offsets.  sumM_max / sumN_max bound the totals (default: the size of w and
-    of r).  Returns r (indices local to each filter)."""
-    import torch
-    _dev_tensor(w, "w")
-    _dev_tensor(w_off, "w_off", torch.int64)
-    _dev_tensor(n_off, "n_off", torch.int64)
-    B = w_off.numel() - 1
-    if n_off.numel() != B + 1:
-        raise ValueError("w_off and n_off must have the same length")
-    p = precision_of(w)
-    sumM = int(w.numel() if sumM_max is None else sumM_max)
-    if r is None:
-        if sumN_max is None:
-            raise ValueError("give r or sumN_max")
-        r = torch.empty(max(int(sumN_max), 1), dtype=torch.int32, device=w.device)
-    sumN = int(r.numel() if sumN_max is None else sumN_max)
-    _dev_tensor(r, "r", torch.int32, sumN)
-    _dev_tensor(seg_status, "seg_status", torch.int32, B)
-    _dev_tensor(dev_status, "dev_status", torch.int32, 1)
-    need = dcr_batched_workspace_bytes(B, sumM, sumN, p)
-    if ws is None:
-        ws = torch.empty(need, dtype=torch.uint8, device=w.device)
-    _dev_tensor(ws, "ws")
+    of r; sumM_max may not exceed the size of w).  Returns r (indices local to
+    each filter)."""
+    B, p, sumM, sumN, r, ws = _batched_args(w, w_off, n_off, sumM_max, sumN_max, r, seg_status,
+                                            dev_status, ws)
     _check("dcr_resample_batched", library().dcr_resample_batched(
         _ptr(w), _ptr(w_off), _ptr(n_off), B, sumM, sumN, int(seed), p, _ptr(r),
         _ptr(seg_status), _ptr(dev_status), _ptr(ws), ws.numel(), _stream(w.device)))

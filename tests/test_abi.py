@@ -232,3 +232,20 @@ def test_binding_rejects_host_and_mistyped_tensors(lib):
     with pytest.raises(ValueError):
         dcr.dcr_resample_batched(w, torch.zeros(2, dtype=torch.int64),
                                  torch.zeros(2, dtype=torch.int64), 1, sumN_max=1)
+
+
+def test_binding_rejects_weight_bound_beyond_weights(lib, monkeypatch):
+    """A sumM_max larger than w would let device-checked offsets run past the
+    weights: every batched wrapper refuses it before any call."""
+    torch = pytest.importorskip("torch")
+    import paper_2604_01356_amd as dcr
+    from paper_2604_01356_amd import _binding
+    # the checks run before the tensors' device is used: stand-in device tensors
+    monkeypatch.setattr(_binding, "_dev_tensor", lambda *a, **k: None)
+    w = torch.ones(100, dtype=torch.float32)
+    off = torch.zeros(3, dtype=torch.int64)
+    for fn in (dcr.dcr_resample_batched, dcr.dcr_resample_batched_ex):
+        with pytest.raises(ValueError, match="exceeds"):
+            fn(w, off, off, 1, sumM_max=101, sumN_max=10)
+    with pytest.raises(ValueError, match="exceeds"):
+        dcr.dcr_batched_autotune(w, off, off, sumM_max=101, sumN_max=10)
