@@ -11,9 +11,11 @@
  *
  * Conventions shared by every entry point
  *   - Memory: every array argument is a caller-owned DEVICE pointer (for
- *     example a torch tensor's data_ptr()).  The library never allocates or
- *     frees device memory; scratch space is the caller's workspace `ws` of
- *     `ws_bytes` bytes, sized by dcr_workspace_bytes() and 256-byte aligned.
+ *     example a torch tensor's data_ptr()).  The library allocates and frees
+ *     device memory only in dcr_plan_create_batched / dcr_plan_destroy; the
+ *     other calls use the caller's workspace `ws` of `ws_bytes` bytes, sized
+ *     by dcr_workspace_bytes() and 256-byte aligned (dcr_resample_noalloc a
+ *     static device array).
  *   - Streams: calls enqueue kernels on `stream` and return without
  *     synchronising; results are valid once the stream has reached them.
  *     Calls on different streams must not share a workspace.
@@ -227,6 +229,56 @@ dcr_status dcr_batched_autotune(const void* w, const int64_t* w_off, const int64
                                 dcr_precision p, int32_t* r, void* ws, size_t ws_bytes,
                                 const char* cache_path, int32_t* best_chunk, float* best_ms,
                                 hipStream_t stream);
+
+/* Batched plans (the batched form above with its resources held between
+ * calls): a plan owns a device workspace for up to B_max filters with at most
+ * sumM_max weights and sumN_max draws in total, the map tile for that shape,
+ * and a HIP graph of the four batched launches.  Filter b of a call is, as in
+ * dcr_resample_batched, an independent problem of Sec. I-III with Philox
+ * stream id b, resampled by Alg. 5 on its own weights.
+ *
+ * dcr_plan_create_batched: allocates the workspace (the only entry point
+ *   besides dcr_plan_destroy that allocates or frees device memory) on the
+ *   current device.  tune_cache: NULL, or the path of the autotuner's text
+ *   cache; a line "B_max sumM_max sumN_max precision chunk ms" with the
+ *   plan's shape sets the map tile, else it is the default (512) until
+ *   dcr_plan_autotune.  *out receives the plan (NULL on error).
+ *   Errors: those of dcr_batched_workspace_bytes; DCR_ERR_HIP if the
+ *   allocation fails. */
+typedef struct dcr_plan_s* dcr_plan;
+dcr_status dcr_plan_create_batched(int32_t B_max, int64_t sumM_max, int64_t sumN_max,
+                                   dcr_precision p, const char* tune_cache, dcr_plan* out);
+
+/* dcr_plan_resample_batched: dcr_resample_batched with the plan's workspace and
+ * map tile, launched as the plan's graph.  Arguments as dcr_resample_batched
+ * with 1 <= B <= B_max and the plan's precision and capacities (offsets whose
+ * totals exceed them give DCR_ERR_CAPACITY_EXCEEDED in *dev_status, as
+ * there); the indices equal that call's bit for bit.  The first call builds
+ * the graph; later calls write their arguments (pointers, B, seed) into its
+ * kernel nodes and launch it, so pointers may change from call to call.  The
+ * call is asynchronous on `stream`; it waits on the host only when the caller
+ * is more than one call of this plan ahead of the device.  A plan serves one
+ * caller at a time: calls on it must not overlap (different threads or
+ * streams), and it must be used on the device it was created on
+ * (DCR_ERR_INVALID_ARGUMENT otherwise). */
+dcr_status dcr_plan_resample_batched(dcr_plan plan, const void* w, const int64_t* w_off,
+                                     const int64_t* n_off, int32_t B, uint64_t seed, int32_t* r,
+                                     int32_t* seg_status, int32_t* dev_status,
+                                     hipStream_t stream);
+
+/* dcr_plan_autotune: times the map tiles on the caller's batch
+ * (dcr_batched_autotune with the plan's workspace; r is overwritten), keeps
+ * the fastest in the plan and appends it to the plan's tune cache, if any.
+ * Waits for the stream.  *best_ms (may be NULL) receives its milliseconds per
+ * call.  dcr_plan_map_chunk reports the plan's current map tile. */
+dcr_status dcr_plan_autotune(dcr_plan plan, const void* w, const int64_t* w_off,
+                             const int64_t* n_off, int32_t B, uint64_t seed, int32_t* r,
+                             float* best_ms, hipStream_t stream);
+dcr_status dcr_plan_map_chunk(dcr_plan plan, int32_t* chunk);
+
+/* dcr_plan_destroy: waits for the plan's launches, then frees its graph and
+ * workspace.  DCR_ERR_INVALID_ARGUMENT for NULL. */
+dcr_status dcr_plan_destroy(dcr_plan plan);
 
 /* Allocation-free end to end, for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid

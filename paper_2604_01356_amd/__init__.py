@@ -17,6 +17,11 @@ from ._binding import (  # noqa: F401
     dcr_batched_workspace_bytes,
     dcr_cumulative_weights,
     dcr_inverse_cmf,
+    dcr_plan_autotune,
+    dcr_plan_create_batched,
+    dcr_plan_destroy,
+    dcr_plan_map_chunk,
+    dcr_plan_resample_batched,
     dcr_profile_begin,
     dcr_profile_end,
     dcr_resample,

@@ -83,6 +83,16 @@ def library():
     lib.dcr_resample_noalloc.argtypes = [P, i64, i64, u64, u64, ctypes.c_int, ctypes.c_int, P, P,
                                          P, P, P]
     lib.dcr_resample_noalloc.restype = ctypes.c_int
+    lib.dcr_plan_create_batched.argtypes = [i32, i64, i64, ctypes.c_int, ctypes.c_char_p, P]
+    lib.dcr_plan_create_batched.restype = ctypes.c_int
+    lib.dcr_plan_resample_batched.argtypes = [P, P, P, P, i32, u64, P, P, P, P]
+    lib.dcr_plan_resample_batched.restype = ctypes.c_int
+    lib.dcr_plan_autotune.argtypes = [P, P, P, P, i32, u64, P, P, P]
+    lib.dcr_plan_autotune.restype = ctypes.c_int
+    lib.dcr_plan_map_chunk.argtypes = [P, P]
+    lib.dcr_plan_map_chunk.restype = ctypes.c_int
+    lib.dcr_plan_destroy.argtypes = [P]
+    lib.dcr_plan_destroy.restype = ctypes.c_int
     lib.dcr_profile_begin.argtypes = [i32]
     lib.dcr_profile_begin.restype = ctypes.c_int
     lib.dcr_profile_end.argtypes = [i32, P, P]
@@ -393,6 +403,68 @@ def dcr_resample_batched(w, w_off, n_off, seed: int, sumM_max: int | None = None
         _ptr(w), _ptr(w_off), _ptr(n_off), B, sumM, sumN, int(seed), p, _ptr(r),
         _ptr(seg_status), _ptr(dev_status), _ptr(ws), ws.numel(), _stream(w.device)))
     return r
+
+
+def dcr_plan_create_batched(B_max: int, sumM_max: int, sumN_max: int,
+                            precision: int = DCR_FP32_COMP, tune_cache=None) -> int:
+    """A batched plan on the current device (its workspace and graph); returns
+    the handle, to be released with dcr_plan_destroy."""
+    h = ctypes.c_void_p(0)
+    _check("dcr_plan_create_batched", library().dcr_plan_create_batched(
+        int(B_max), int(sumM_max), int(sumN_max), int(precision),
+        None if tune_cache is None else str(tune_cache).encode(), ctypes.byref(h)))
+    return int(h.value)
+
+
+def _plan_args(w, w_off, n_off, r, seg_status, dev_status):
+    import torch
+    _dev_tensor(w, "w")
+    _dev_tensor(w_off, "w_off", torch.int64)
+    _dev_tensor(n_off, "n_off", torch.int64)
+    B = w_off.numel() - 1
+    if n_off.numel() != B + 1:
+        raise ValueError("w_off and n_off must have the same length")
+    _dev_tensor(r, "r", torch.int32)
+    _dev_tensor(seg_status, "seg_status", torch.int32, B)
+    _dev_tensor(dev_status, "dev_status", torch.int32, 1)
+    return B
+
+
+def dcr_plan_resample_batched(plan: int, w, w_off, n_off, seed: int, r, seg_status=None,
+                              dev_status=None):
+    """B filters with the plan's workspace, map tile and graph (r: int32
+    device tensor holding at least the plan's sumN_max draws)."""
+    B = _plan_args(w, w_off, n_off, r, seg_status, dev_status)
+    with __import__("torch").cuda.device(w.device):
+        code = library().dcr_plan_resample_batched(
+            ctypes.c_void_p(plan), _ptr(w), _ptr(w_off), _ptr(n_off), B, int(seed), _ptr(r),
+            _ptr(seg_status), _ptr(dev_status), _stream(w.device))
+    _check("dcr_plan_resample_batched", code)
+    return r
+
+
+def dcr_plan_autotune(plan: int, w, w_off, n_off, r, seed: int = 0) -> float:
+    """Times the map tiles on this batch and keeps the fastest in the plan;
+    returns its milliseconds per call."""
+    B = _plan_args(w, w_off, n_off, r, None, None)
+    ms = ctypes.c_float(0.0)
+    with __import__("torch").cuda.device(w.device):
+        code = library().dcr_plan_autotune(
+            ctypes.c_void_p(plan), _ptr(w), _ptr(w_off), _ptr(n_off), B, int(seed), _ptr(r),
+            ctypes.addressof(ms), _stream(w.device))
+    _check("dcr_plan_autotune", code)
+    return float(ms.value)
+
+
+def dcr_plan_map_chunk(plan: int) -> int:
+    c = ctypes.c_int32(0)
+    _check("dcr_plan_map_chunk", library().dcr_plan_map_chunk(ctypes.c_void_p(plan),
+                                                             ctypes.addressof(c)))
+    return int(c.value)
+
+
+def dcr_plan_destroy(plan: int):
+    _check("dcr_plan_destroy", library().dcr_plan_destroy(ctypes.c_void_p(plan)))
 
 
 def dcr_profile_begin(cap: int):

@@ -7,6 +7,8 @@
 #include <cstdint>
 #include <cstdio>
 #include <mutex>
+#include <new>
+#include <string>
 #include <vector>
 
 #include "dcr.h"
@@ -207,6 +209,40 @@ BatchLayout make_batch_layout(int64_t B, int64_t sumM, int64_t sumN) {
     return L;
 }
 
+// Argument block of the batched launches.  The layout is sized for B_layout
+// filters (B itself for a stateless call, a plan's B_max), of which the call
+// uses B.
+dcr::BatchArgs batch_args(const BatchLayout& L, void* ws, const int64_t* w_off,
+                          const int64_t* n_off, int32_t B, int64_t B_layout, int32_t chunk,
+                          uint64_t seed, int64_t sumM_max, int64_t sumN_max,
+                          int32_t* seg_status) {
+    dcr::BatchArgs ba{};
+    ba.w_off = w_off;
+    ba.n_off = n_off;
+    ba.B = B;
+    ba.chunk = chunk;
+    ba.seed = seed;
+    ba.wt_cap = L.wt_cap;
+    ba.zt_cap = L.zt_cap;
+    ba.mc_cap = (sumN_max + chunk - 1) / chunk + B_layout;
+    ba.sumM_cap = sumM_max;
+    ba.sumN_cap = sumN_max;
+    ba.wt_base = at<int64_t>(ws, L.wt_base);
+    ba.zt_base = at<int64_t>(ws, L.zt_base);
+    ba.mc_base = at<int64_t>(ws, L.mc_base);
+    ba.head = at<int32_t>(ws, L.head);
+    ba.wt_tot = at<double>(ws, L.wt_tot);
+    ba.wt_beta = at<double>(ws, L.wt_beta);
+    ba.wt_sub = at<double>(ws, L.wt_sub);
+    ba.wt_chunk = at<double>(ws, L.wt_chunk);
+    ba.zt_tot = at<double>(ws, L.zt_tot);
+    ba.zt_beta = at<double>(ws, L.zt_beta);
+    ba.zrel = at<double>(ws, L.zrel);
+    ba.seg_status = seg_status ? seg_status : at<int32_t>(ws, L.seg_status);
+    ba.seg_totals = at<double>(ws, L.seg_totals);
+    return ba;
+}
+
 bool batch_sizes_ok(int64_t B, int64_t sumM, int64_t sumN) {
     if (B < 1 || B > kMaxBatch || sumM < B || sumM > kMaxSum || sumN < 0 || sumN > kMaxSum)
         return false;
@@ -240,6 +276,16 @@ bool cache_lookup(const char* path, int64_t B, int64_t sumM, int64_t sumN, int p
     }
     std::fclose(f);
     return found;
+}
+
+void cache_store(const char* path, int64_t B, int64_t sumM, int64_t sumN, int p, int32_t chunk,
+                 float ms) {
+    if (!path) return;
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%lld %lld %lld %d %d %.6f\n", static_cast<long long>(B),
+                 static_cast<long long>(sumM), static_cast<long long>(sumN), p, chunk, ms);
+    std::fclose(f);
 }
 
 }  // namespace
@@ -482,30 +528,8 @@ dcr_status dcr_resample_batched_ex(const void* w, const int64_t* w_off, const in
     if ((reinterpret_cast<uintptr_t>(ws) & 255u) != 0) return DCR_ERR_INVALID_ARGUMENT;
     const BatchLayout L = make_batch_layout(B, sumM_max, sumN_max);
     if (ws_bytes < L.bytes) return DCR_ERR_WORKSPACE_TOO_SMALL;
-    dcr::BatchArgs ba{};
-    ba.w_off = w_off;
-    ba.n_off = n_off;
-    ba.B = B;
-    ba.chunk = chunk;
-    ba.seed = seed;
-    ba.wt_cap = L.wt_cap;
-    ba.zt_cap = L.zt_cap;
-    ba.mc_cap = (sumN_max + chunk - 1) / chunk + B;
-    ba.sumM_cap = sumM_max;
-    ba.sumN_cap = sumN_max;
-    ba.wt_base = at<int64_t>(ws, L.wt_base);
-    ba.zt_base = at<int64_t>(ws, L.zt_base);
-    ba.mc_base = at<int64_t>(ws, L.mc_base);
-    ba.head = at<int32_t>(ws, L.head);
-    ba.wt_tot = at<double>(ws, L.wt_tot);
-    ba.wt_beta = at<double>(ws, L.wt_beta);
-    ba.wt_sub = at<double>(ws, L.wt_sub);
-    ba.wt_chunk = at<double>(ws, L.wt_chunk);
-    ba.zt_tot = at<double>(ws, L.zt_tot);
-    ba.zt_beta = at<double>(ws, L.zt_beta);
-    ba.zrel = at<double>(ws, L.zrel);
-    ba.seg_status = seg_status ? seg_status : at<int32_t>(ws, L.seg_status);
-    ba.seg_totals = at<double>(ws, L.seg_totals);
+    const dcr::BatchArgs ba =
+        batch_args(L, ws, w_off, n_off, B, B, chunk, seed, sumM_max, sumN_max, seg_status);
     const int prec = prec_code(p);
     hipError_t e = timed(kKBatchPlan, stream, [&] { return dcr::launch_batch_plan(ba, dev_status, stream); });
     if (e == hipSuccess)
@@ -567,15 +591,7 @@ dcr_status dcr_batched_autotune(const void* w, const int64_t* w_off, const int64
     if (st != DCR_OK) return st;
     *best_chunk = pick;
     if (best_ms) *best_ms = best;
-    if (cache_path) {
-        FILE* f = std::fopen(cache_path, "a");
-        if (f) {
-            std::fprintf(f, "%lld %lld %lld %d %d %.6f\n", static_cast<long long>(B),
-                         static_cast<long long>(sumM_max), static_cast<long long>(sumN_max),
-                         static_cast<int>(p), pick, best);
-            std::fclose(f);
-        }
-    }
+    cache_store(cache_path, B, sumM_max, sumN_max, static_cast<int>(p), pick, best);
     return DCR_OK;
 }
 
@@ -634,6 +650,182 @@ int32_t dcr_profile_kind_count(void) { return kNumKinds; }
 
 const char* dcr_profile_kind_name(int32_t kind) {
     return (kind >= 0 && kind < kNumKinds) ? kKindNames[kind] : "";
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched plans: a device workspace sized once, the map tile from the tune
+// cache (or the autotuner), and a HIP graph of the four batched launches built
+// node by node.  Each call writes its arguments (pointers, B, seed) into the
+// kernel nodes of an instantiated graph and launches it.  Two instances
+// alternate, each with an event recorded after its last launch: before an
+// instance's nodes are rewritten, the event is waited on, so a launch still
+// in flight never sees the next call's arguments (a wait happens only when a
+// caller runs more than one call ahead of the device).
+// ---------------------------------------------------------------------------
+struct dcr_plan_s {
+    int32_t B_max = 0;
+    int64_t sumM_max = 0, sumN_max = 0;
+    dcr_precision p = DCR_FP64;
+    int32_t chunk = dcr::kBatchChunkDefault;
+    int device = -1;
+    std::string cache_path;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    struct Instance {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        hipGraphNode_t nodes[4] = {};
+        hipEvent_t done = nullptr;
+        int32_t chunk = 0;   // the map tile the graph was built for
+        bool launched = false;
+    };
+    Instance inst[2];
+    int next = 0;
+};
+
+namespace {
+
+void release_instance(dcr_plan_s::Instance& in) {
+    if (in.exec) (void)hipGraphExecDestroy(in.exec);
+    if (in.graph) (void)hipGraphDestroy(in.graph);
+    if (in.done) (void)hipEventDestroy(in.done);
+    in = dcr_plan_s::Instance{};
+}
+
+// Builds (or rebuilds, after a change of map tile) an instance's graph from
+// the call's arguments.
+dcr_status build_instance(dcr_plan_s& pl, dcr_plan_s::Instance& in, dcr::BatchNodeArgs& a) {
+    release_instance(in);
+    hipKernelNodeParams kp[4];
+    if (dcr::batched_node_params(prec_code(pl.p), a, pl.B_max, kp) != hipSuccess)
+        return DCR_ERR_INTERNAL;
+    if (hipEventCreateWithFlags(&in.done, hipEventDisableTiming) != hipSuccess ||
+        hipGraphCreate(&in.graph, 0) != hipSuccess) {
+        release_instance(in);
+        return DCR_ERR_HIP;
+    }
+    for (int k = 0; k < 4; ++k) {
+        const hipGraphNode_t* dep = (k == 0) ? nullptr : &in.nodes[k - 1];
+        if (hipGraphAddKernelNode(&in.nodes[k], in.graph, dep, k == 0 ? 0 : 1, &kp[k]) !=
+            hipSuccess) {
+            release_instance(in);
+            return DCR_ERR_HIP;
+        }
+    }
+    if (hipGraphInstantiate(&in.exec, in.graph, nullptr, nullptr, 0) != hipSuccess) {
+        release_instance(in);
+        return DCR_ERR_HIP;
+    }
+    in.chunk = a.ba.chunk;
+    return DCR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dcr_status dcr_plan_create_batched(int32_t B_max, int64_t sumM_max, int64_t sumN_max,
+                                   dcr_precision p, const char* tune_cache, dcr_plan* out) {
+    if (!out) return DCR_ERR_INVALID_ARGUMENT;
+    *out = nullptr;
+    if (!batch_sizes_ok(B_max, sumM_max, sumN_max)) return DCR_ERR_INVALID_ARGUMENT;
+    if (!valid_prec(p)) return DCR_ERR_UNSUPPORTED;
+    dcr_plan_s* pl = new (std::nothrow) dcr_plan_s();
+    if (!pl) return DCR_ERR_INTERNAL;
+    pl->B_max = B_max;
+    pl->sumM_max = sumM_max;
+    pl->sumN_max = sumN_max;
+    pl->p = p;
+    if (tune_cache) pl->cache_path = tune_cache;
+    int32_t cached = 0;
+    if (cache_lookup(tune_cache, B_max, sumM_max, sumN_max, static_cast<int>(p), &cached))
+        pl->chunk = cached;
+    pl->ws_bytes = make_batch_layout(B_max, sumM_max, sumN_max).bytes;
+    if (hipGetDevice(&pl->device) != hipSuccess || hipMalloc(&pl->ws, pl->ws_bytes) != hipSuccess) {
+        delete pl;
+        return DCR_ERR_HIP;
+    }
+    *out = pl;
+    return DCR_OK;
+}
+
+dcr_status dcr_plan_destroy(dcr_plan plan) {
+    if (!plan) return DCR_ERR_INVALID_ARGUMENT;
+    dcr_status st = DCR_OK;
+    for (auto& in : plan->inst)
+        if (in.done && in.launched && hipEventSynchronize(in.done) != hipSuccess) st = DCR_ERR_HIP;
+    for (auto& in : plan->inst) release_instance(in);
+    if (plan->ws && hipFree(plan->ws) != hipSuccess) st = DCR_ERR_HIP;
+    delete plan;
+    return st;
+}
+
+dcr_status dcr_plan_map_chunk(dcr_plan plan, int32_t* chunk) {
+    if (!plan || !chunk) return DCR_ERR_INVALID_ARGUMENT;
+    *chunk = plan->chunk;
+    return DCR_OK;
+}
+
+dcr_status dcr_plan_resample_batched(dcr_plan plan, const void* w, const int64_t* w_off,
+                                     const int64_t* n_off, int32_t B, uint64_t seed, int32_t* r,
+                                     int32_t* seg_status, int32_t* dev_status,
+                                     hipStream_t stream) {
+    if (!plan || !w || !w_off || !n_off || B < 1 || B > plan->B_max ||
+        (plan->sumN_max > 0 && !r))
+        return DCR_ERR_INVALID_ARGUMENT;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return DCR_ERR_HIP;
+    if (dev != plan->device) return DCR_ERR_INVALID_ARGUMENT;
+    const BatchLayout L = make_batch_layout(plan->B_max, plan->sumM_max, plan->sumN_max);
+    dcr::BatchNodeArgs a{};
+    a.ba = batch_args(L, plan->ws, w_off, n_off, B, plan->B_max, plan->chunk, seed,
+                      plan->sumM_max, plan->sumN_max, seg_status);
+    a.w = w;
+    a.r = r;
+    a.dev_status = dev_status;
+    dcr_plan_s::Instance& in = plan->inst[plan->next];
+    if (!in.exec || in.chunk != plan->chunk) {
+        if (in.launched && hipEventSynchronize(in.done) != hipSuccess) return DCR_ERR_HIP;
+        const dcr_status st = build_instance(*plan, in, a);
+        if (st != DCR_OK) return st;
+    } else {
+        // the previous launch of this instance has read its arguments
+        if (in.launched && hipEventSynchronize(in.done) != hipSuccess) return DCR_ERR_HIP;
+        hipKernelNodeParams kp[4];
+        if (dcr::batched_node_params(prec_code(plan->p), a, plan->B_max, kp) != hipSuccess)
+            return DCR_ERR_INTERNAL;
+        for (int k = 0; k < 4; ++k)
+            if (hipGraphExecKernelNodeSetParams(in.exec, in.nodes[k], &kp[k]) != hipSuccess)
+                return DCR_ERR_HIP;
+    }
+    if (hipGraphLaunch(in.exec, stream) != hipSuccess) return DCR_ERR_HIP;
+    if (hipEventRecord(in.done, stream) != hipSuccess) return DCR_ERR_HIP;
+    in.launched = true;
+    plan->next ^= 1;
+    return DCR_OK;
+}
+
+dcr_status dcr_plan_autotune(dcr_plan plan, const void* w, const int64_t* w_off,
+                             const int64_t* n_off, int32_t B, uint64_t seed, int32_t* r,
+                             float* best_ms, hipStream_t stream) {
+    if (!plan) return DCR_ERR_INVALID_ARGUMENT;
+    if (B < 1 || B > plan->B_max) return DCR_ERR_INVALID_ARGUMENT;
+    // the plan's graphs may still be reading the workspace
+    for (auto& in : plan->inst)
+        if (in.launched && hipEventSynchronize(in.done) != hipSuccess) return DCR_ERR_HIP;
+    int32_t best = 0;
+    float ms = 0.0f;
+    const dcr_status st =
+        dcr_batched_autotune(w, w_off, n_off, B, plan->sumM_max, plan->sumN_max, seed, plan->p,
+                             r, plan->ws, plan->ws_bytes, nullptr, &best, &ms, stream);
+    if (st != DCR_OK) return st;
+    plan->chunk = best;   // the graphs are rebuilt for it on their next use
+    if (best_ms) *best_ms = ms;
+    cache_store(plan->cache_path.empty() ? nullptr : plan->cache_path.c_str(), plan->B_max,
+                plan->sumM_max, plan->sumN_max, static_cast<int>(plan->p), best, ms);
+    return DCR_OK;
 }
 
 }  // extern "C"

@@ -1775,7 +1775,9 @@ __global__ __launch_bounds__(kThreads) void k_reduce_batched(const Tin* __restri
 // One workgroup per filter: its block-total scans, totals and status.
 __global__ __launch_bounds__(kScanThreads) void k_carries_batched(BatchArgs ba) {
     __shared__ ScanLds L;
-    if (ba.head[0] != kStatusOk) return;
+    // a plan's graph launches one workgroup per filter it can hold; those
+    // beyond the call's B have nothing to do
+    if (ba.head[0] != kStatusOk || static_cast<int>(blockIdx.x) >= ba.B) return;
     const int b = blockIdx.x;
     const SharedArgs sh = seg_shared(ba, b);
     // a filter's few block totals: fewer of them held in registers (the
@@ -2400,6 +2402,56 @@ static void launch_map_batched_t(const Tin* w, const BatchArgs& ba, int32_t* r, 
         launch(k_map_batched<Tin, 1024, 64>, dim3(grid), dim3(kThreads), 0, s, w, ba, r, dev_status);
     else
         launch(k_map_batched<Tin, 512, 64>, dim3(grid), dim3(kThreads), 0, s, w, ba, r, dev_status);
+}
+
+// The four batched launches as kernel nodes of a HIP graph (the order of
+// launch_batch_plan .. launch_map_batched, with the same grids; carries takes
+// `carry_wgs` workgroups, at least ba.B).  The argument blocks of `out` point
+// into `a`, which must outlive the use of `out`.
+hipError_t batched_node_params(int prec, BatchNodeArgs& a, int carry_wgs,
+                               hipKernelNodeParams (&out)[4]) {
+    const BatchArgs& ba = a.ba;
+    if (ba.chunk != 256 && ba.chunk != 512 && ba.chunk != 1024) return hipErrorInvalidValue;
+    a.argv[0][0] = &a.ba;
+    a.argv[0][1] = &a.dev_status;
+    a.argv[1][0] = &a.w;
+    a.argv[1][1] = &a.ba;
+    a.argv[2][0] = &a.ba;
+    a.argv[3][0] = &a.w;
+    a.argv[3][1] = &a.ba;
+    a.argv[3][2] = &a.r;
+    a.argv[3][3] = &a.dev_status;
+    const bool f32 = prec == kPrecFP32;
+    void* map = nullptr;
+    if (ba.chunk == 256)
+        map = f32 ? reinterpret_cast<void*>(&k_map_batched<float, 256, 32>)
+                  : reinterpret_cast<void*>(&k_map_batched<double, 256, 32>);
+    else if (ba.chunk == 1024)
+        map = f32 ? reinterpret_cast<void*>(&k_map_batched<float, 1024, 64>)
+                  : reinterpret_cast<void*>(&k_map_batched<double, 1024, 64>);
+    else
+        map = f32 ? reinterpret_cast<void*>(&k_map_batched<float, 512, 64>)
+                  : reinterpret_cast<void*>(&k_map_batched<double, 512, 64>);
+    void* const funcs[4] = {
+        reinterpret_cast<void*>(&k_batch_plan),
+        f32 ? reinterpret_cast<void*>(&k_reduce_batched<float, kPrecFP32>)
+            : reinterpret_cast<void*>(&k_reduce_batched<double, kPrecFP64>),
+        reinterpret_cast<void*>(&k_carries_batched), map};
+    const dim3 grids[4] = {dim3(1), dim3(static_cast<unsigned>(ba.zt_cap + ba.wt_cap)),
+                           dim3(static_cast<unsigned>(carry_wgs)),
+                           dim3(static_cast<unsigned>(ba.mc_cap))};
+    const dim3 blocks[4] = {dim3(kPlanThreads), dim3(kThreads), dim3(kScanThreads),
+                            dim3(kThreads)};
+    for (int k = 0; k < 4; ++k) {
+        out[k] = hipKernelNodeParams{};
+        out[k].func = funcs[k];
+        out[k].gridDim = grids[k];
+        out[k].blockDim = blocks[k];
+        out[k].sharedMemBytes = 0;
+        out[k].kernelParams = a.argv[k];
+        out[k].extra = nullptr;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_map_batched(int prec, const void* w, const BatchArgs& ba, int32_t* r,

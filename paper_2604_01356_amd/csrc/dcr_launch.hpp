@@ -71,4 +71,17 @@ hipError_t launch_carries_batched(const BatchArgs& ba, hipStream_t s);
 hipError_t launch_map_batched(int prec, const void* w, const BatchArgs& ba, int32_t* r,
                               int32_t* dev_status, hipStream_t s);
 
+// The same four launches as kernel nodes of a graph (batched plans).  The
+// argument blocks point into BatchNodeArgs, which the caller keeps alive while
+// it adds or updates the nodes.
+struct BatchNodeArgs {
+    BatchArgs ba;
+    const void* w;
+    int32_t* r;
+    int32_t* dev_status;
+    void* argv[4][4];
+};
+hipError_t batched_node_params(int prec, BatchNodeArgs& a, int carry_wgs,
+                               hipKernelNodeParams (&out)[4]);
+
 }  // namespace dcr

@@ -199,6 +199,25 @@ def test_host_validation_noalloc(lib):
     assert n.value > (32 << 20)
 
 
+def test_host_validation_plan(lib):
+    """Plan calls refuse bad arguments before any allocation or launch."""
+    h = ctypes.c_void_p(0)
+    f = lib.dcr_plan_create_batched
+    assert f(0, 1000, 10, 1, None, ctypes.byref(h)) == 1            # B_max < 1
+    assert f(8, 4, 10, 1, None, ctypes.byref(h)) == 1               # sumM_max < B_max
+    assert f(8, 1000, -1, 1, None, ctypes.byref(h)) == 1
+    assert f(8, 1 << 41, 10, 1, None, ctypes.byref(h)) == 1
+    assert f(8, 1000, 10, 4, None, ctypes.byref(h)) == 2            # unknown precision
+    assert f(8, 1000, 10, 1, None, None) == 1                       # no output handle
+    assert h.value is None
+    g = lib.dcr_plan_resample_batched
+    assert g(None, FAKE, FAKE, FAKE, 1, 0, FAKE, None, None, None) == 1
+    assert lib.dcr_plan_destroy(None) == 1
+    assert lib.dcr_plan_autotune(None, FAKE, FAKE, FAKE, 1, 0, FAKE, None, None) == 1
+    c = ctypes.c_int32(0)
+    assert lib.dcr_plan_map_chunk(None, ctypes.byref(c)) == 1
+
+
 def test_profile_api_host(lib):
     assert lib.dcr_profile_kind_count() >= 5
     names = [lib.dcr_profile_kind_name(k).decode() for k in range(lib.dcr_profile_kind_count())]
