@@ -175,6 +175,66 @@ def calibrate_copy():
                       "bytes_written": CALIBRATE_BYTES}), flush=True)
 
 
+def host_info() -> dict:
+    """The host the CPU rows ran on: CPU model and the cores this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
+def measure_copy_bw(dcr, torch, dev, reps: int = 10) -> dict:
+    """Streaming references measured in the same run on 1 GiB (beyond the
+    Infinity Cache): the library's streaming read and copy kernels (coalesced
+    16-byte loads, best of a few grid sizes) and torch's copy_, each the
+    median of `reps` launches."""
+    import statistics
+    n = CALIBRATE_BYTES // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+
+    def med(fn):
+        for _ in range(2):
+            fn()
+        times = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1) * 1e-3)
+        return statistics.median(times)
+
+    res = {"read_gbs": 0.0, "copy_gbs": 0.0}
+    for unroll in (4, 8, 16):
+        for grid in (1024, 2048, 4096, 8192, 16384):
+            t = med(lambda: dcr.dcr_stream_probe(0, src, dst, grid, unroll))
+            if CALIBRATE_BYTES / t / 1e9 > res["read_gbs"]:
+                res["read_gbs"], res["read_launch"] = CALIBRATE_BYTES / t / 1e9, [grid, unroll]
+            t = med(lambda: dcr.dcr_stream_probe(1, src, dst, grid, unroll))
+            if 2 * CALIBRATE_BYTES / t / 1e9 > res["copy_gbs"]:
+                res["copy_gbs"], res["copy_launch"] = 2 * CALIBRATE_BYTES / t / 1e9, [grid, unroll]
+    res["torch_copy_gbs"] = 2 * CALIBRATE_BYTES / med(lambda: dst.copy_(src)) / 1e9
+    res["note"] = ("1 GiB: read = bytes read / time, copy = bytes read + written / time; "
+                   f"median of {reps} launches; best [grid, loads in flight] of the sweep")
+    del src, dst
+    torch.cuda.empty_cache()
+    return res
+
+
 def batched_reduce_bytes(w_off, n_off, s_w: int) -> int:
     """Algorithmic HBM bytes of the batched reduce launch: every filter's
     weights once, its sub-tile ends and block totals, its N_b + 1 spacing
@@ -252,6 +312,27 @@ def measure_batched(dcr, torch, dev, steps: int, warmup: int, cpu_seconds: float
     torch.cuda.synchronize()
     graph_equal = bool(torch.equal(r_g, r))
     del g
+    # the library's own plan: its workspace, tuned tile and graph (launched
+    # with hipGraphLaunch, the arguments written into the graph's nodes)
+    plan = dcr.dcr_plan_create_batched(bw.B, w32.size, sumN, dcr.DCR_FP32_COMP)
+    try:
+        r_p = torch.empty_like(r)
+        dcr.dcr_plan_autotune(plan, w, w_off, n_off, r_p, seed=0)
+        for k in range(warmup):
+            dcr.dcr_plan_resample_batched(plan, w, w_off, n_off, k, r_p, None, st)
+        torch.cuda.synchronize()
+        e0.record()
+        for k in range(steps):
+            dcr.dcr_plan_resample_batched(plan, w, w_off, n_off, k, r_p, None, st)
+        e1.record()
+        torch.cuda.synchronize()
+        plan_ms = e0.elapsed_time(e1) / steps
+        plan_chunk = dcr.dcr_plan_map_chunk(plan)
+        dcr.dcr_plan_resample_batched(plan, w, w_off, n_off, 0, r_p, None, st)
+        torch.cuda.synchronize()
+        plan_equal = bool(torch.equal(r_p, r)) and int(st.item()) == 0
+    finally:
+        dcr.dcr_plan_destroy(plan)
     r0 = r.cpu().numpy()
     red_bytes = batched_reduce_bytes(bw.w_off, bw.n_off, 4)
     achieved = red_bytes / (kernels["batch_reduce"] * 1e-3) / 1e9
@@ -265,6 +346,9 @@ def measure_batched(dcr, torch, dev, steps: int, warmup: int, cpu_seconds: float
         "unit": "particles/s",
         "graph_ms_per_step": graph_ms,
         "graph_equals_eager": graph_equal,
+        "plan_ms_per_step": plan_ms,
+        "plan_map_chunk": plan_chunk,
+        "plan_equals_eager": plan_equal,
         "weights_per_s": w32.size / (ms * 1e-3),
         "step_weight_gbs": w32.nbytes / (ms * 1e-3) / 1e9,
         "kernels_ms": kernels,
@@ -275,24 +359,21 @@ def measure_batched(dcr, torch, dev, steps: int, warmup: int, cpu_seconds: float
     }
     if cpu_seconds > 0:
         import oracle
-        # the oracle on a bounded sample: the first filters until the time is spent
+        # the oracle over every filter of the batch, its filters spread over
+        # the host's cores by OpenMP (each filter's arithmetic unchanged)
+        threads = int(os.environ.get("OMP_NUM_THREADS") or 0) or host_info()["usable_cpus"]
         t0 = time.perf_counter()
-        done_n = 0
-        mism = 0
-        b = 0
-        while b < bw.B and time.perf_counter() - t0 < cpu_seconds:
-            a, e = bw.w_off[b], bw.w_off[b + 1]
-            Nb = int(bw.n_off[b + 1] - bw.n_off[b])
-            rb = oracle.resample(w32[a:e], Nb, seed=0, stream=b)[0]
-            mism += int(np.sum(rb != r0[bw.n_off[b]:bw.n_off[b + 1]]))
-            done_n += Nb
-            b += 1
+        r_or, used = oracle.resample_batched_parallel(w32, bw.w_off, bw.n_off, 0, threads)
         t = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": done_n / t, "unit": "particles/s", "cores": 1,
+        mism = int(np.sum(r_or != r0))
+        out["cpu_baseline"] = {"value": sumN / t, "unit": "particles/s", "cores": used,
                                "kind": "oracle",
-                               "sample": f"oracle on filters 0..{b - 1} of the batch "
-                                         f"({done_n} draws) in {t:.1f} s, single thread"}
-        out["mismatches_vs_oracle_sample"] = mism
+                               "sample": f"oracle on all {bw.B} filters ({sumN} draws) in "
+                                         f"{t:.2f} s, OpenMP over filters on {used} threads"}
+        # the binary32 form against the oracle on the same binary32 weights:
+        # every mismatch is a bin-edge case (device and host logf differ by an ulp)
+        out["mismatches_vs_oracle"] = mism
+        out["mismatch_rate_vs_oracle"] = mism / sumN
     del w, ws, r
     torch.cuda.empty_cache()
     return out
@@ -470,10 +551,36 @@ def measure_small(dcr, torch, dev, reps: int = 200):
                 torch.cuda.synchronize()
                 return e0.elapsed_time(e1) / reps * 1e3
 
+            def single(fn, n=50):
+                # one call on an idle device: events around it, median
+                import statistics
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                lat = []
+                for _ in range(n):
+                    torch.cuda.synchronize()
+                    e0.record()
+                    fn()
+                    e1.record()
+                    torch.cuda.synchronize()
+                    lat.append(e0.elapsed_time(e1) * 1e3)
+                return statistics.median(lat)
+
+            def host_issue(fn, n=200):
+                # host time to enqueue one call (no wait)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(n):
+                    fn()
+                t1 = time.perf_counter()
+                torch.cuda.synchronize()
+                return (t1 - t0) / n * 1e6
+
+            eager_fn = lambda: dcr.dcr_resample(w, wl.N, 0, r=r_e, ws=ws)  # noqa: E731
             for _ in range(3):
-                dcr.dcr_resample(w, wl.N, 0, r=r_e, ws=ws)
+                eager_fn()
             torch.cuda.synchronize()
-            eager_us = timed(lambda: dcr.dcr_resample(w, wl.N, 0, r=r_e, ws=ws))
+            eager_us = timed(eager_fn)
             s = torch.cuda.Stream()
             s.wait_stream(torch.cuda.current_stream())
             g = torch.cuda.CUDAGraph()
@@ -490,6 +597,10 @@ def measure_small(dcr, torch, dev, reps: int = 200):
                 "M": wl.M, "N": wl.N,
                 "us_per_call_eager": eager_us,
                 "us_per_call_graph": graph_us,
+                "single_call_us_eager": single(eager_fn),
+                "single_call_us_graph": single(g.replay),
+                "host_issue_us_eager": host_issue(eager_fn),
+                "host_issue_us_graph": host_issue(g.replay),
                 "graph_equals_eager": bool(torch.equal(r_g, r_e)),
             }
             del g, ws
@@ -578,6 +689,16 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         ms_step = e0.elapsed_time(e1) / steps
+        # pass 1b: every step bracketed by its own events, for the median
+        import statistics
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(steps)]
+        for k in range(steps):
+            evs[k][0].record()
+            step(k)
+            evs[k][1].record()
+        torch.cuda.synchronize()
+        ms_median = statistics.median(a.elapsed_time(b) for a, b in evs)
         # pass 2: per-kernel HIP events on the launch stream
         dcr.dcr_profile_begin(steps * 8)
         for k in range(steps):
@@ -601,10 +722,11 @@ def main():
             del t
         del ws_copies
         torch.cuda.empty_cache()
-        return ms_step, kernels, r0, w_host, W0
+        return ms_step, kernels, r0, w_host, W0, ms_median
 
+    copy_bw = measure_copy_bw(dcr, torch, dev)
     want_w = not args.no_cpu and args.precision == "f32"
-    ms, kernels, r_gpu, w_host, W_gpu = measure(args.precision, args.steps, args.warmup)
+    ms, kernels, r_gpu, w_host, W_gpu, ms_med = measure(args.precision, args.steps, args.warmup)
     want_w = False
     s_w = 4 if args.precision == "f32" else 8
     touched = int(len(np.unique(r_gpu // W_SUB)))
@@ -626,6 +748,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms,
+        "ms_per_step_median": ms_med,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -652,22 +775,28 @@ def main():
             "traffic": traffic,
             "algorithmic_bytes": dom_bytes,
             "avg_launch_us": kernels[dom] * 1e3,
+            "frac_of_copy": achieved / copy_bw["copy_gbs"],
+            "frac_of_read": achieved / copy_bw["read_gbs"],
         },
+        "device_copy_bw": copy_bw,
     }
     if not args.no_compare:
         other = "f64" if args.precision == "f32" else "f32"
-        ms_o, kern_o, _, _, _ = measure(other, max(5, args.steps // 2), 2)
+        ms_o, kern_o, _, _, _, med_o = measure(other, max(5, args.steps // 2), 2)
         out[f"compare_{other}"] = {
             "ms_per_step": ms_o,
+            "ms_per_step_median": med_o,
             "value": wl.N / (ms_o * 1e-3),
             "speedup_of_headline": ms_o / ms,
             "kernels_ms": kern_o,
         }
     if not args.no_cpu:
         cb, r_or = cpu_baseline(wl, w_host, args.cpu_seconds)
+        cb["host"] = host_info()
         out["cpu_baseline"] = cb
         out["cpu_paper_algorithm"] = cpu_paper_algorithm(wl, w_host, args.cpu_seconds / 2)
         out["mismatches_vs_oracle_seed0"] = int(np.sum(r_gpu != r_or))
+        out["mismatch_rate_vs_oracle_seed0"] = float(np.mean(r_gpu != r_or))
         if W_gpu is not None:
             # the binary32-input result against the oracle on the binary64 weights
             import oracle
@@ -689,15 +818,24 @@ def main():
         out["stages"] = measure_stages(dcr, torch, dev, wl, args.precision,
                                        max(5, args.steps // 5))
     if args.workload != "equal" and not args.no_equal:
-        # the equal-size instance (linear-merge limit of the map), binary32 form
+        # the equal-size instance (linear-merge limit of the map), both forms
         wl_eq = workloads.CONFIGS["equal"]()
         wl_saved = wl
         wl = wl_eq
-        ms_e, kern_e, _, _, _ = measure("f32", max(5, args.steps // 5), 2)
+        out["equal"] = {"workload": wl_eq.description}
+        for prec in ("f32", "f64"):
+            ms_e, kern_e, r_e, w_e, _, med_e = measure(prec, max(5, args.steps // 5), 2)
+            row = {"ms_per_step": ms_e, "ms_per_step_median": med_e,
+                   "value": wl_eq.N / (ms_e * 1e-3), "unit": "particles/s", "kernels_ms": kern_e}
+            if not args.no_cpu:
+                import oracle
+                r_o = oracle.resample(w_e, wl_eq.N, seed=0, stream=0)[0]
+                row["mismatches_vs_oracle_seed0"] = int(np.sum(r_e != r_o))
+                row["mismatch_rate_vs_oracle_seed0"] = float(np.mean(r_e != r_o))
+            out["equal"][prec] = row
+        out["equal"]["speedup_f32_over_f64"] = (out["equal"]["f64"]["ms_per_step"] /
+                                                out["equal"]["f32"]["ms_per_step"])
         wl = wl_saved
-        out["equal"] = {"workload": wl_eq.description, "ms_per_step": ms_e,
-                        "value": wl_eq.N / (ms_e * 1e-3), "unit": "particles/s",
-                        "kernels_ms": kern_e}
     print(json.dumps(out), flush=True)
 
 

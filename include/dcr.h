@@ -318,6 +318,16 @@ dcr_status dcr_profile_end(int32_t n_kinds, int64_t* counts, double* ms);
 int32_t dcr_profile_kind_count(void);
 const char* dcr_profile_kind_name(int32_t kind);
 
+/* Bandwidth reference for measurement (not part of the sampling contract):
+ * kind 0 streams `bytes` from src (coalesced 16-byte loads, `unroll` = 4, 8
+ * or 16 in flight per thread) and writes one float partial sum per workgroup
+ * to dst (grid floats); kind 1 copies `bytes` from src to dst.  `grid`
+ * workgroups of 256 threads.  src and dst 16-byte aligned, bytes a positive
+ * multiple of 16; otherwise DCR_ERR_INVALID_ARGUMENT.  Asynchronous on
+ * `stream`. */
+dcr_status dcr_stream_probe(int32_t kind, int32_t unroll, const void* src, void* dst,
+                            size_t bytes, int32_t grid, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

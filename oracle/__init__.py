@@ -82,6 +82,8 @@ def _load():
     lib.dcro_resample_repeat.restype = i32
     lib.dcro_resample_batched.argtypes = [P, i32, P, P, i64, u64, i32, P]
     lib.dcro_resample_batched.restype = i32
+    lib.dcro_resample_batched_par.argtypes = [P, i32, P, P, i64, u64, i32, i32, P, P]
+    lib.dcro_resample_batched_par.restype = i32
     lib.dcro_scheme_uniforms.argtypes = [i64, u64, u64, i32, P]
     lib.dcro_scheme_uniforms.restype = i32
     lib.dcro_resample_scheme.argtypes = [P, i32, i64, i64, u64, u64, i32, P, P, P]
@@ -293,6 +295,28 @@ def resample_repeat(w: np.ndarray, N: int, seed0: int, R: int) -> np.ndarray:
     if st != OK:
         raise OracleError(f"resample_repeat: status {st}")
     return r[:, :N]
+
+
+def resample_batched_parallel(w: np.ndarray, w_off: np.ndarray, n_off: np.ndarray, seed: int,
+                              threads: int, zkind: int | None = None):
+    """resample_batched with the filters spread over OpenMP threads (the same
+    per-filter arithmetic); returns (r, threads used)."""
+    import ctypes
+    w = np.ascontiguousarray(w)
+    w_off = np.ascontiguousarray(w_off, dtype=np.int64)
+    n_off = np.ascontiguousarray(n_off, dtype=np.int64)
+    B = w_off.shape[0] - 1
+    is_f32 = 1 if w.dtype == np.float32 else 0
+    if not is_f32:
+        w = _f64(w)
+    zk = (1 if is_f32 else 0) if zkind is None else zkind
+    r = np.empty(max(int(n_off[-1]), 1), dtype=np.int32)
+    used = ctypes.c_int(0)
+    st = _load().dcro_resample_batched_par(_ptr(w), is_f32, _ptr(w_off), _ptr(n_off), B, seed, zk,
+                                           int(threads), _ptr(r), ctypes.addressof(used))
+    if st != OK:
+        raise OracleError(f"resample_batched_parallel: status {st}")
+    return r[: int(n_off[-1])], int(used.value)
 
 
 def resample_batched(w: np.ndarray, w_off: np.ndarray, n_off: np.ndarray, seed: int,

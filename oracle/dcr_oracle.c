@@ -37,6 +37,7 @@
  * worked example, a separately written library Philox, and distribution laws).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -431,18 +432,54 @@ int dcro_resample_repeat(const double* w, int64_t M, int64_t N, uint64_t seed0, 
 /* Batched form: filter b resamples its own segment w[w_off[b] .. w_off[b+1])
  * into r[n_off[b] .. n_off[b+1]) with stream id b; indices are local to the
  * segment.  Returns the first failing filter's status. */
+static int resample_filter(const void* w, int is_f32, const int64_t* w_off, const int64_t* n_off,
+                           int64_t b, uint64_t seed, int zkind, int32_t* r)
+{
+    int64_t M = w_off[b + 1] - w_off[b];
+    int64_t N = n_off[b + 1] - n_off[b];
+    const void* wb = is_f32 ? (const void*)((const float*)w + w_off[b])
+                            : (const void*)((const double*)w + w_off[b]);
+    return resample_impl(wb, is_f32, M, N, seed, (uint64_t)b, zkind, r + n_off[b], NULL, NULL);
+}
+
 int dcro_resample_batched(const void* w, int is_f32, const int64_t* w_off, const int64_t* n_off,
                           int64_t B, uint64_t seed, int zkind, int32_t* r)
 {
     int st_all = DCRO_OK;
     for (int64_t b = 0; b < B; ++b) {
-        int64_t M = w_off[b + 1] - w_off[b];
-        int64_t N = n_off[b + 1] - n_off[b];
-        const void* wb = is_f32 ? (const void*)((const float*)w + w_off[b])
-                                : (const void*)((const double*)w + w_off[b]);
-        int st = resample_impl(wb, is_f32, M, N, seed, (uint64_t)b, zkind, r + n_off[b], NULL,
-                               NULL);
+        int st = resample_filter(w, is_f32, w_off, n_off, b, seed, zkind, r);
         if (st != DCRO_OK && st_all == DCRO_OK) st_all = st;
     }
     return st_all;
+}
+
+/* The same with the filters spread over `nthreads` OpenMP threads (each
+ * filter's arithmetic is unchanged, so the result equals the loop above).
+ * Returns the status of the lowest-numbered failing filter; *threads_used
+ * (if not NULL) receives the team size. */
+int dcro_resample_batched_par(const void* w, int is_f32, const int64_t* w_off,
+                              const int64_t* n_off, int64_t B, uint64_t seed, int zkind,
+                              int nthreads, int32_t* r, int* threads_used)
+{
+    int64_t first_bad = B;
+    int st_bad = DCRO_OK;
+    int team = 1;
+#pragma omp parallel num_threads(nthreads > 0 ? nthreads : 1)
+    {
+#pragma omp single
+        team = omp_get_num_threads();
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t b = 0; b < B; ++b) {
+            int st = resample_filter(w, is_f32, w_off, n_off, b, seed, zkind, r);
+            if (st != DCRO_OK) {
+#pragma omp critical
+                if (b < first_bad) {
+                    first_bad = b;
+                    st_bad = st;
+                }
+            }
+        }
+    }
+    if (threads_used) *threads_used = team;
+    return st_bad;
 }

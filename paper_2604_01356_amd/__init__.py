@@ -33,6 +33,7 @@ from ._binding import (  # noqa: F401
     dcr_scheme_uniforms,
     dcr_sorted_uniforms,
     dcr_status_string,
+    dcr_stream_probe,
     dcr_workspace_bytes,
     library,
     library_path,

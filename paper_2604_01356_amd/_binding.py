@@ -93,6 +93,8 @@ def library():
     lib.dcr_plan_map_chunk.restype = ctypes.c_int
     lib.dcr_plan_destroy.argtypes = [P]
     lib.dcr_plan_destroy.restype = ctypes.c_int
+    lib.dcr_stream_probe.argtypes = [i32, i32, P, P, sz, i32, P]
+    lib.dcr_stream_probe.restype = ctypes.c_int
     lib.dcr_profile_begin.argtypes = [i32]
     lib.dcr_profile_begin.restype = ctypes.c_int
     lib.dcr_profile_end.argtypes = [i32, P, P]
@@ -465,6 +467,16 @@ def dcr_plan_map_chunk(plan: int) -> int:
 
 def dcr_plan_destroy(plan: int):
     _check("dcr_plan_destroy", library().dcr_plan_destroy(ctypes.c_void_p(plan)))
+
+
+def dcr_stream_probe(kind: int, src, dst, grid: int, unroll: int = 8):
+    """Bandwidth reference (measurement only): kind 0 reads src (dst receives
+    `grid` float partial sums), kind 1 copies src to dst."""
+    _dev_tensor(src, "src")
+    _dev_tensor(dst, "dst")
+    nbytes = src.numel() * src.element_size()
+    _check("dcr_stream_probe", library().dcr_stream_probe(
+        int(kind), int(unroll), _ptr(src), _ptr(dst), nbytes, int(grid), _stream(src.device)))
 
 
 def dcr_profile_begin(cap: int):

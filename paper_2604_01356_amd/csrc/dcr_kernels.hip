@@ -2152,6 +2152,51 @@ __global__ __launch_bounds__(kThreads) void k_map_batched(const Tin* __restrict_
 }
 
 // ---------------------------------------------------------------------------
+// Bandwidth reference for measurement (not part of the method): a streaming
+// read of n 16-byte pieces (summed, one partial sum per workgroup) and a
+// streaming copy, each thread keeping U coalesced 16-byte loads in flight,
+// the access pattern the weight stream of k_reduce aims at.
+// ---------------------------------------------------------------------------
+template <int U>
+__global__ __launch_bounds__(kThreads) void k_stream_read(const f32x4* __restrict__ src, int64_t n,
+                                                          float* __restrict__ part) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kThreads;
+    int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (; i + (U - 1) * stride < n; i += U * stride) {
+        f32x4 v[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) v[k] = src[i + k * stride];
+#pragma unroll
+        for (int k = 0; k < U; ++k) acc += v[k];
+    }
+    for (; i < n; i += stride) acc += src[i];
+    __shared__ float red[kThreads];
+    red[threadIdx.x] = acc.x + acc.y + acc.z + acc.w;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float t = 0.f;
+        for (int k = 0; k < kThreads; ++k) t += red[k];
+        part[blockIdx.x] = t;
+    }
+}
+
+template <int U>
+__global__ __launch_bounds__(kThreads) void k_stream_copy(const f32x4* __restrict__ src, int64_t n,
+                                                          f32x4* __restrict__ dst) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * kThreads;
+    int64_t i = static_cast<int64_t>(blockIdx.x) * kThreads + threadIdx.x;
+    for (; i + (U - 1) * stride < n; i += U * stride) {
+        f32x4 v[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) v[k] = src[i + k * stride];
+#pragma unroll
+        for (int k = 0; k < U; ++k) dst[i + k * stride] = v[k];
+    }
+    for (; i < n; i += stride) dst[i] = src[i];
+}
+
+// ---------------------------------------------------------------------------
 // Host-side launchers
 // ---------------------------------------------------------------------------
 // Every kernel launch of the library goes through here: the launch records
@@ -2370,6 +2415,28 @@ hipError_t launch_map_w(const double* W, int64_t M, const double* u, int64_t N, 
     return hipGetLastError();
 }
 
+
+template <int U>
+static void launch_stream_probe_t(int kind, const void* src, void* dst, int64_t pieces, int grid,
+                                  hipStream_t s) {
+    if (kind == 0)
+        launch(k_stream_read<U>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s,
+               static_cast<const f32x4*>(src), pieces, static_cast<float*>(dst));
+    else
+        launch(k_stream_copy<U>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s,
+               static_cast<const f32x4*>(src), pieces, static_cast<f32x4*>(dst));
+}
+
+hipError_t launch_stream_probe(int kind, int unroll, const void* src, void* dst, int64_t pieces,
+                               int grid, hipStream_t s) {
+    if (unroll == 16)
+        launch_stream_probe_t<16>(kind, src, dst, pieces, grid, s);
+    else if (unroll == 8)
+        launch_stream_probe_t<8>(kind, src, dst, pieces, grid, s);
+    else
+        launch_stream_probe_t<4>(kind, src, dst, pieces, grid, s);
+    return hipGetLastError();
+}
 
 hipError_t launch_batch_plan(const BatchArgs& ba, int32_t* dev_status, hipStream_t s) {
     launch(k_batch_plan, dim3(1), dim3(kPlanThreads), 0, s, ba, dev_status);

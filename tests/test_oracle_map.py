@@ -117,3 +117,19 @@ def test_table1_comparison_counts(oracle_mod, ratio):
     assert c_dac <= 3.0 * N * math.log2(M / N + 1) + 2 * N
     if ratio >= 100:
         assert c_dac < c_ccf and c_dac < c_bin
+
+
+def test_batched_parallel_equals_sequential(oracle_mod):
+    """The OpenMP loop over filters (the batched CPU baseline) changes no
+    filter's arithmetic: its result equals the sequential loop's."""
+    rng = np.random.Generator(np.random.PCG64(44))
+    Mb = rng.integers(1, 6000, 40)
+    Nb = rng.integers(0, 400, 40)
+    w_off = np.concatenate([[0], np.cumsum(Mb)]).astype(np.int64)
+    n_off = np.concatenate([[0], np.cumsum(Nb)]).astype(np.int64)
+    for dtype in (np.float64, np.float32):
+        w = np.exp(rng.normal(0.0, 3.0, int(w_off[-1]))).astype(dtype)
+        seq = oracle_mod.resample_batched(w, w_off, n_off, 9)
+        par, used = oracle_mod.resample_batched_parallel(w, w_off, n_off, 9, 3)
+        assert used >= 1
+        assert np.array_equal(seq, par)
