@@ -14,8 +14,12 @@
 //               end of sub-tile s)
 //   array       block totals scanned by a monotone two-level scan (carries)
 //               into beta_1..beta_nb (beta_0 = 0, beta_nb = total);
-//               S_j = min(beta_b + S_blk, beta_{b+1}), and S_j = beta_{b+1} at
-//               the last element of block b.
+//               S_j = min(beta_b + S_blk, beta_{b+1}), and S_j = beta_{b+1}
+//               once S_blk has reached the block total (block_end_at; always
+//               at the block's last element).  A weight of zero therefore
+//               ends exactly where the previous weight does, also across
+//               lane-chunk, sub-tile and block boundaries (the scan keeps a
+//               zero block total's end at the previous end).
 //
 // Every level either adds a non-negative local prefix to a base computed by
 // the same left-to-right rule (monotone because round-to-nearest is monotone)
@@ -353,6 +357,17 @@ __device__ __forceinline__ double raw_sum(const RawChunk<Tin>& r, Tin& mn) {
         mn = fmin(mn, r.raw(k));
     }
     return s;
+}
+
+// Unnormalised cumulative weight at the end of an element of block b (or of a
+// lane chunk or sub-tile, at its last element): y is its in-block prefix, X
+// the block's total (its last stored sub-tile end), beta_b and beta_n the
+// scanned ends of blocks b-1 and b.  A prefix that has reached the block total
+// is the block end itself, so the weights of zero after a block's last
+// positive weight end exactly where it does (an empty interval: never drawn);
+// the prefix of the block's last element always equals X.
+__device__ __forceinline__ double block_end_at(double y, double X, double beta_b, double beta_n) {
+    return (y == X) ? beta_n : fmin(beta_b + y, beta_n);
 }
 
 // A weight is admissible iff it is finite and >= 0 (NaN fails both tests).

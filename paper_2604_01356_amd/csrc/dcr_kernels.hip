@@ -428,8 +428,13 @@ __global__ __launch_bounds__(kThreads) void k_reduce(const Tin* __restrict__ w, 
 // thread totals (DPP wave scans, then the 4 wave totals left to right) made
 // non-decreasing by a running maximum; then
 //     out_j = min(gamma_t + p_j, gamma_{t+1}),
-// which is non-decreasing for non-negative input.  A NaN or infinite total
-// (an inadmissible block) sets the sequence's `bad` flag.
+// which is non-decreasing for non-negative input.  Zero totals keep the
+// output exactly where it was (a bin of weight zero gets an empty interval):
+// the outputs of a thread whose running sum has reached its total (unless it
+// ends the sequence) are gamma_{t+1} itself, and the base that follows a
+// thread with a zero total does not enter the running maximum, so
+// gamma_{t+1} = gamma_t there; zeros inside a thread's range add nothing to p.  A NaN or infinite total (an inadmissible block)
+// sets the sequence's `bad` flag.
 // ---------------------------------------------------------------------------
 constexpr int kScanThreads = kThreads;
 constexpr int kScanWaves = kScanThreads / 64;
@@ -459,6 +464,7 @@ struct ScanLds {
     double wtot[2][kScanWaves];
     double wmax[2][kScanWaves];
     int wbad[2][kScanWaves];
+    int wlastz[2][kScanWaves];   // the wave's last thread has a zero total
     double last[2];
     double spare[2];   // receives the unused outputs of a thread's last registers
 };
@@ -516,7 +522,10 @@ __device__ void scan_pair(const ScanIn<R> (&si)[2], const ScanOut (&so)[2], Scan
         const double incl = wave_incl_add(tt);
         excl[q] = wave_shift_up1(incl);
         const bool wave_bad = __builtin_amdgcn_ballot_w64(nonfinite != 0) != 0;
-        if (lane64 == 63) L.wtot[q][wid] = incl;
+        if (lane64 == 63) {
+            L.wtot[q][wid] = incl;
+            L.wlastz[q][wid] = (tt == 0.0) ? 1 : 0;
+        }
         if (lane64 == 0) L.wbad[q][wid] = wave_bad ? 1 : 0;
     }
     lds_barrier();
@@ -535,7 +544,15 @@ __device__ void scan_pair(const ScanIn<R> (&si)[2], const ScanOut (&so)[2], Scan
         for (int k = 0; k < kScanWaves; ++k)
             if (k < wid) s = s + w4[k];
         wb[q] = s;
-        wmx[q] = wave_incl_max(s + excl[q]);
+        // the previous thread's total is zero: this base stays out of the
+        // running maximum (0 is its identity for non-negative values)
+        const double prev_thr = wave_shift_up1(thr[q]);
+        int prev_zero = 0;
+#pragma unroll
+        for (int k = 0; k < kScanWaves; ++k)
+            if (k + 1 == wid) prev_zero = L.wlastz[q][k];
+        prev_zero = (lane64 == 0) ? prev_zero : (prev_thr == 0.0 ? 1 : 0);
+        wmx[q] = wave_incl_max(prev_zero ? 0.0 : s + excl[q]);
         if (lane64 == 63) L.wmax[q][wid] = wmx[q];
     }
     lds_barrier();
@@ -562,8 +579,14 @@ __device__ void scan_pair(const ScanIn<R> (&si)[2], const ScanOut (&so)[2], Scan
 #pragma unroll
             for (int k = 0; k < kScanWaves; ++k)
                 if (k == wid) wbn = wbn + w4[k];
+            if (thr[q] == 0.0) wbn = 0.0;   // kept out of the running maximum
             gnext = (wid == kScanWaves - 1) ? __builtin_huge_val() : fmax(wbn, prev_next);
         }
+        // once a thread's running sum has reached its total (its last positive
+        // total and the zeros after it), the output is the next base itself,
+        // unless the thread ends the sequence (a thread whose total is zero
+        // has gnext == gamma already)
+        const bool pin = thr[q] > 0.0 && si[q].e < so[q].n;
         const int64_t a = si[q].a, e = si[q].e, n = so[q].n;
         double p = 0.0;
         if (si[q].in_regs) {
@@ -576,7 +599,7 @@ __device__ void scan_pair(const ScanIn<R> (&si)[2], const ScanOut (&so)[2], Scan
 #pragma unroll
             for (int k = 0; k < R; ++k) {
                 if (k < si[q].per) {
-                    const double o = fmin(gamma + pre[q][k], gnext);
+                    const double o = (pin && pre[q][k] == thr[q]) ? gnext : fmin(gamma + pre[q][k], gnext);
                     if (so[q].out_lds) *((k < cnt) ? dst + k : &L.spare[q]) = o;
                     if (so[q].out_gl && k < cnt) so[q].out_gl[a + k] = o;
                 }
@@ -594,7 +617,7 @@ __device__ void scan_pair(const ScanIn<R> (&si)[2], const ScanOut (&so)[2], Scan
                     const int64_t j = j0 + k;
                     if (j < e) {
                         p = p + x[k];
-                        const double o = fmin(gamma + p, gnext);
+                        const double o = (pin && p == thr[q]) ? gnext : fmin(gamma + p, gnext);
                         if (so[q].out_lds) so[q].out_lds[j] = o;
                         if (so[q].out_gl) so[q].out_gl[j] = o;
                         if (j == n - 1) L.last[q] = o;
@@ -742,6 +765,7 @@ __device__ __forceinline__ void k_materialize_w_body(Src w, WArgs wa, SharedArgs
     const int status = sh.status[0];
     const double total = sh.totals[0];
     const double sigma = (s == 0) ? 0.0 : wa.sub_end[b * kWSubPerBlock + s - 1];
+    const double X = wa.sub_end[b * kWSubPerBlock + kWSubPerBlock - 1];
     const double beta_b = (b == 0) ? 0.0 : wa.beta[b - 1];
     const double beta_n = wa.beta[b];
     double p[kLane];
@@ -758,13 +782,9 @@ __device__ __forceinline__ void k_materialize_w_body(Src w, WArgs wa, SharedArgs
     for (int k = 0; k < kRowLanes; ++k)
         if (k < lane) c = c + lv[k];
     if (status != kStatusOk) return;   // workgroup-uniform
-    const int64_t jlast = ((blk0 + kWBlock < wa.M) ? blk0 + kWBlock : wa.M) - 1;
     double out[kLane];
 #pragma unroll
-    for (int k = 0; k < kLane; ++k) {
-        const double S = (j0 + k == jlast) ? beta_n : fmin(beta_b + (sigma + (c + p[k])), beta_n);
-        out[k] = S / total;
-    }
+    for (int k = 0; k < kLane; ++k) out[k] = block_end_at(sigma + (c + p[k]), X, beta_b, beta_n) / total;
     if (full && (vec_ok & 2)) {
 #pragma unroll
         for (int k = 0; k < kLane; ++k) stage[t * kLane + k] = out[k];
@@ -848,7 +868,7 @@ constexpr int64_t kFinishResident = 512;  // k_finish workgroups the chip holds 
 struct SubtileLoc {
     int64_t b, blk0, jlast;
     int s, nsub;
-    double beta_b, beta_n, sigma;
+    double beta_b, beta_n, sigma, X;   // X: the block's total (its last sub-tile end)
 };
 
 __device__ SubtileLoc locate_subtile(const WArgs& wa, const double* sbeta, int64_t kstride,
@@ -903,10 +923,13 @@ __device__ SubtileLoc locate_subtile(const WArgs& wa, const double* sbeta, int64
         }
     }
     auto se_index = [qi](int k) { return 2 * kQuad * (k >> 1) + 2 * qi + (k & 1); };
+    // the block total: the last stored end, held by lane 3 of the quad
+    const double X = quad_bcast(e[kPerLane - 1], kQuad - 1);
+    L.X = X;
     int cnt = 0;
 #pragma unroll
     for (int k = 0; k < kPerLane; ++k)
-        cnt += (se_index(k) < nsub - 1 && fmin(beta_b + e[k], beta_n) < x) ? 1 : 0;
+        cnt += (se_index(k) < nsub - 1 && block_end_at(e[k], X, beta_b, beta_n) < x) ? 1 : 0;
     const int s = quad_sum(cnt);
     L.s = s;
     // sigma_s = stored end of sub-tile s-1, taken from the lane that read it
@@ -948,6 +971,7 @@ __device__ int64_t locate_subtile_index(const WArgs& wa, const double* sbeta, in
     // the block's 128 stored ends, read as in locate_subtile: lane qi takes
     // the 16-byte pieces qi, qi + 4, ..., four at a time
     const f64x2* se = reinterpret_cast<const f64x2*>(wa.sub_end + b * kWSubPerBlock) + qi;
+    const double X = wa.sub_end[b * kWSubPerBlock + kWSubPerBlock - 1];   // the block total
     constexpr int kPieces = kWSubPerBlock / (2 * kQuad);   // per lane
     int cnt = 0;
     for (int v4 = 0; v4 < kPieces; v4 += 4) {
@@ -955,8 +979,8 @@ __device__ int64_t locate_subtile_index(const WArgs& wa, const double* sbeta, in
         for (int v = v4; v < v4 + 4; ++v) {
             const f64x2 d = se[kQuad * v];
             const int s0 = 2 * kQuad * v + 2 * qi;
-            cnt += (s0 < nsub - 1 && fmin(beta_b + d.x, beta_n) < x) ? 1 : 0;
-            cnt += (s0 + 1 < nsub - 1 && fmin(beta_b + d.y, beta_n) < x) ? 1 : 0;
+            cnt += (s0 < nsub - 1 && block_end_at(d.x, X, beta_b, beta_n) < x) ? 1 : 0;
+            cnt += (s0 + 1 < nsub - 1 && block_end_at(d.y, X, beta_b, beta_n) < x) ? 1 : 0;
         }
     }
     return b * kWSubPerBlock + quad_sum(cnt);
@@ -968,8 +992,8 @@ __device__ void map_quad(Src w, const WArgs& wa, const double* sbeta, int64_t ks
     using Elem = typename SrcElem<Src>::type;
     const SubtileLoc loc = locate_subtile(wa, sbeta, kstride, ns, x, qi);
     const int64_t blk0 = loc.blk0, jlast = loc.jlast;
-    const int s = loc.s, nsub = loc.nsub;
-    const double beta_b = loc.beta_b, beta_n = loc.beta_n, sigma = loc.sigma;
+    const int s = loc.s;
+    const double beta_b = loc.beta_b, beta_n = loc.beta_n, sigma = loc.sigma, X = loc.X;
     const int64_t sub0 = blk0 + static_cast<int64_t>(s) * kSub;
     const int slen = static_cast<int>((jlast - sub0 + 1 < kSub) ? jlast - sub0 + 1 : kSub);
     const int nl = (slen + kLane - 1) / kLane;
@@ -1005,7 +1029,6 @@ __device__ void map_quad(Src w, const WArgs& wa, const double* sbeta, int64_t ks
     // added by the lane that holds chunk l and passed to the whole quad, so
     // the sums are the same additions in the same order as one lane running
     // over all 16 chunks; cb[q] = start of chunk qi + 4q
-    const bool last_sub = (s == nsub - 1);   // its last chunk ends at beta_{b+1}
     double cb[kChunks];
     {
         double run = 0.0;   // c_l, the same in every lane of the quad
@@ -1029,8 +1052,7 @@ __device__ void map_quad(Src w, const WArgs& wa, const double* sbeta, int64_t ks
 #pragma unroll
     for (int q = kChunks - 1; q >= 0; --q) {
         const int l = qi + kQuad * q;
-        const double en =
-            (last_sub && l == nl - 1) ? beta_n : fmin(beta_b + (sigma + (cb[q] + tl[q])), beta_n);
+        const double en = block_end_at(sigma + (cb[q] + tl[q]), X, beta_b, beta_n);
         lmine = (l < nl && en >= x) ? l : lmine;
     }
     int lf = min(lmine, dpp_i32<kDppQuadSwap1>(lmine));
@@ -1063,8 +1085,7 @@ __device__ void map_quad(Src w, const WArgs& wa, const double* sbeta, int64_t ks
 #pragma unroll
     for (int k = 0; k < kLane; ++k) {
         pk = pk + xx[k];
-        const int64_t j = l0 + k;
-        const double en = (j == jlast) ? beta_n : fmin(beta_b + (sigma + (cf + pk)), beta_n);
+        const double en = block_end_at(sigma + (cf + pk), X, beta_b, beta_n);
         hit |= (k < nv && en >= x) ? (1u << k) : 0u;
     }
     const int64_t jr = hit ? l0 + __builtin_ctz(hit) : l0 + nv - 1;
@@ -1280,9 +1301,10 @@ __device__ __forceinline__ void k_map_dense_body(Src w, WArgs wa, ZArgs za, Shar
         const int64_t j0 = blk0 + static_cast<int64_t>(sb) * kSub + lane * kLane;
         const int nv = (row < nw) ? clamp_count(wa.M - j0, kLane) : 0;
         // every load of the window first: its weights and the bases they need
-        double sigma = 0.0, beta_b = 0.0, beta_n = 0.0;
+        double sigma = 0.0, beta_b = 0.0, beta_n = 0.0, X = 0.0;
         if (nv > 0) {
             sigma = (sb == 0) ? 0.0 : wa.sub_end[b * kWSubPerBlock + sb - 1];
+            X = wa.sub_end[b * kWSubPerBlock + kWSubPerBlock - 1];
             beta_b = (b == 0) ? 0.0 : wa.beta[b - 1];
             beta_n = wa.beta[b];
         }
@@ -1298,12 +1320,11 @@ __device__ __forceinline__ void k_map_dense_body(Src w, WArgs wa, ZArgs za, Shar
         for (int k = 0; k < lane; ++k) c = c + ltot[row * kRowLanes + k];
         // normalised cumulative weights (the in-chunk prefixes summed again
         // from the raw values, same order); entries past the weights read +inf
-        const int64_t jlast = ((blk0 + kWBlock < wa.M) ? blk0 + kWBlock : wa.M) - 1;
         double pk = 0.0;
 #pragma unroll
         for (int k = 0; k < kLane; ++k) {
             pk = (k == 0) ? rc.at(0) : pk + rc.at(k);
-            const double S = (j0 + k == jlast) ? beta_n : fmin(beta_b + (sigma + (c + pk)), beta_n);
+            const double S = block_end_at(sigma + (c + pk), X, beta_b, beta_n);
             sw[t * kLane + k] = (k < nv) ? S / total : __builtin_huge_val();
         }
         lds_barrier();
@@ -1944,7 +1965,7 @@ __device__ void map_seg_chunk(const Tin* __restrict__ w, const WArgs& wa, const 
     // ---- sub-tile level: first s with end(s) >= x, where
     //      end(s) = min(beta_{b-1} + sigma_{s+1}, beta_b), end(nsub-1) = beta_b ----
     {
-        double bb[kSegPer], bn[kSegPer];
+        double bb[kSegPer], bn[kSegPer], bx[kSegPer];
         int nsub[kSegPer], cnt[kSegPer];
 #pragma unroll
         for (int k = 0; k < kSegPer; ++k) {
@@ -1953,6 +1974,7 @@ __device__ void map_seg_chunk(const Tin* __restrict__ w, const WArgs& wa, const 
             const int64_t b = bk[k];
             bb[k] = (b == 0) ? 0.0 : beta_end(b - 1);
             bn[k] = beta_end(b);
+            bx[k] = sigma_of(b, kWSubPerBlock);   // the block total
             const int64_t blen = (wa.M - b * kWBlock < kWBlock) ? wa.M - b * kWBlock : kWBlock;
             nsub[k] = static_cast<int>((blen + kSub - 1) / kSub);
             cnt[k] = 0;
@@ -1962,7 +1984,7 @@ __device__ void map_seg_chunk(const Tin* __restrict__ w, const WArgs& wa, const 
 #pragma unroll
             for (int k = 0; k < kSegPer; ++k)
                 if (cnt[k] + step <= nsub[k] - 1 &&
-                    fmin(bb[k] + sigma_of(bk[k], cnt[k] + step), bn[k]) < xs[k])
+                    block_end_at(sigma_of(bk[k], cnt[k] + step), bx[k], bb[k], bn[k]) < xs[k])
                     cnt[k] += step;
         }
 #pragma unroll
@@ -2056,7 +2078,7 @@ __device__ void map_seg_chunk(const Tin* __restrict__ w, const WArgs& wa, const 
             int lc[kSegDraws], nv[kSegDraws], nl[kSegDraws];
             int64_t j0[kSegDraws];
             double bb[kSegDraws], bn[kSegDraws], sg[kSegDraws], cl[kSegDraws], xx[kSegDraws];
-            bool eb[kSegDraws];
+            double bx[kSegDraws];
             const double* cr[kSegDraws];
 #pragma unroll
             for (int m = 0; m < kSegDraws; ++m) {
@@ -2075,7 +2097,7 @@ __device__ void map_seg_chunk(const Tin* __restrict__ w, const WArgs& wa, const 
                 bb[m] = (b == 0) ? 0.0 : beta_end(b - 1);
                 bn[m] = beta_end(b);
                 sg[m] = sigma_of(b, s);
-                eb[m] = sub0 + slen - 1 == jlast;
+                bx[m] = sigma_of(b, kWSubPerBlock);   // the block total
                 cr[m] = L.crun + (k - p0) * kRowLanes;
                 j0[m] = sub0;
                 nv[m] = slen;
@@ -2087,7 +2109,8 @@ __device__ void map_seg_chunk(const Tin* __restrict__ w, const WArgs& wa, const 
 #pragma unroll
                 for (int m = 0; m < kSegDraws; ++m)
                     if (lc[m] + step <= nl[m] - 1 &&
-                        fmin(bb[m] + (sg[m] + cr[m][lc[m] + step - 1]), bn[m]) < xx[m])
+                        block_end_at(sg[m] + cr[m][lc[m] + step - 1], bx[m], bb[m], bn[m]) <
+                            xx[m])
                         lc[m] += step;
             }
             RawChunk<Tin> xv[kSegDraws];
@@ -2105,15 +2128,12 @@ __device__ void map_seg_chunk(const Tin* __restrict__ w, const WArgs& wa, const 
             for (int m = 0; m < kSegDraws; ++m) {
                 const int pos = pb + t + m * kThreads;
                 if (pos >= d1) continue;
-                const bool last = eb[m] && lc[m] == nl[m] - 1;
                 double pk = 0.0;
                 int cnt = 0;
 #pragma unroll
                 for (int q = 0; q < kLane; ++q) {
                     pk = pk + xv[m].at(q);
-                    const double S = (last && q == nv[m] - 1)
-                                         ? bn[m]
-                                         : fmin(bb[m] + (sg[m] + (cl[m] + pk)), bn[m]);
+                    const double S = block_end_at(sg[m] + (cl[m] + pk), bx[m], bb[m], bn[m]);
                     cnt += (q < nv[m] && S < xx[m]) ? 1 : 0;
                 }
                 L.sid[pos] = static_cast<int32_t>(j0[m] + cnt);

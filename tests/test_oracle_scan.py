@@ -82,3 +82,19 @@ def test_W_rejects_bad_weights(oracle_mod, bad):
 def test_W_rejects_zero_total(oracle_mod):
     with pytest.raises(oracle_mod.OracleError):
         oracle_mod.cumulative_weights(np.zeros(5))
+
+
+def test_zero_weights_repeat_W_exactly(oracle_mod):
+    """The oracle's exact sums give a weight of zero an empty interval: W_j ==
+    W_{j-1} (and W_0 == 0 for a leading zero), the property the GPU tests pin
+    the blocked sums to."""
+    rng = np.random.Generator(np.random.PCG64(12))
+    w = np.exp(rng.normal(0.0, 3.0, 100_000))
+    w[:50] = 0.0
+    w[rng.random(w.size) < 0.3] = 0.0
+    w[-70:] = 0.0
+    W, _ = oracle_mod.cumulative_weights(w)
+    z = np.flatnonzero(w == 0)
+    assert W[0] == 0.0
+    assert np.array_equal(W[z[z > 0]], W[z[z > 0] - 1])
+    assert W[-1] == 1.0
