@@ -62,6 +62,11 @@ struct SharedArgs {
 // spacing blocks (N + 1 <= 2^18).
 constexpr int kFinishMaxZBlocks = 64;
 
+// Problems of at most this many weight blocks (M <= 2^18) that k_finish
+// takes run k_reduce_small / k_finish_small instead (every round of a block
+// is its own workgroup).
+constexpr int kSmallBlocks = 8;
+
 // N * kDenseRatio >= M: several uniforms per sub-tile on average, mapped by
 // the windowed linear merge (k_map_dense) instead of one search per uniform.
 constexpr int64_t kDenseRatio = 4;

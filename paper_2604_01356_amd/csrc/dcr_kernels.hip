@@ -8,6 +8,9 @@
 //   k_materialize_u     sorted uniforms u (stage 2 output)
 //   k_finish            block scans + uniforms + map in one launch (the common
 //                       end-to-end case)
+//   k_reduce_small, k_finish_small
+//                       the same for at most 8 weight blocks, with one
+//                       workgroup per round of sub-tiles in the reduce
 //   k_map_fused         inverse CMF of u against the cumulative weights kept
 //                       implicit (block bases + sub-tile bases + a rescan of one
 //                       256-weight sub-tile), the divide-and-conquer map of
@@ -1477,6 +1480,173 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
 }
 
 // ---------------------------------------------------------------------------
+// Small problems (at most kSmallBlocks weight blocks): the reduce and the
+// finish split the work differently, with the same sums.  A weight block
+// reduced by one workgroup takes 8 dependent rounds of loads, which is the
+// whole time of a call with only a few blocks; here every round of 16
+// sub-tiles is its own workgroup (k_reduce_small), which stores its 16
+// sub-tile totals, and every k_finish_small workgroup runs the chain of
+// sub-tile ends (sigma, left to right) and the block totals in LDS before
+// the scans, then maps with the sub-tile ends read from LDS.
+// ---------------------------------------------------------------------------
+constexpr int kSmallSub = kSmallBlocks * kWSubPerBlock;
+
+// Round `idx` (block idx / 8, sub-tiles 16 (idx % 8) .. + 15) of the weights:
+// lane-chunk totals left to right, then the 16 sub-tile totals left to right
+// into tau (NaN for a sub-tile holding a negative weight; NaN and infinity
+// reach it through the sums).  All threads call it.
+template <typename Src>
+__device__ __forceinline__ void reduce_small_round(Src w, const WArgs& wa, double* __restrict__ tau,
+                                                   int64_t idx, double* lane_tot) {
+    using Elem = typename SrcElem<Src>::type;
+    const int t = threadIdx.x;
+    const int row = t / kRowLanes;
+    const int lane = t % kRowLanes;
+    const int64_t b = idx / kWIters;
+    const int s = static_cast<int>(idx % kWIters) * kRows + row;
+    const int64_t j0 = b * kWBlock + static_cast<int64_t>(s) * kSub + lane * kLane;
+    const RawChunk<Elem> rc = src_raw_n(w, j0, clamp_count(wa.M - j0, kLane));
+    Elem mn = rc.raw(0);
+    const double tl = raw_sum<Elem>(rc, mn);
+    lane_tot[t] = (mn < static_cast<Elem>(0)) ? __builtin_nan("") : tl;
+    lds_barrier();
+    if (lane == 0) {
+        const double* p = lane_tot + row * kRowLanes;
+        double c = p[0];
+#pragma unroll
+        for (int l = 1; l < kRowLanes; ++l) c = c + p[l];
+        tau[b * kWSubPerBlock + s] = c;
+    }
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(kThreads) void k_reduce_small(const T* __restrict__ w, WArgs wa, ZArgs za,
+                                                          double* __restrict__ tau) {
+    __shared__ double lt[kThreads + kRows];
+    if (static_cast<int64_t>(blockIdx.x) < za.nb) {
+        reduce_z_block<P>(za, blockIdx.x, lt, lt + kThreads);
+        return;
+    }
+    reduce_small_round<const T*>(w, wa, tau, blockIdx.x - za.nb, lt);
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(kThreads) void k_reduce_small_outer(Outer<T> w, WArgs wa, ZArgs za,
+                                                                double* __restrict__ tau) {
+    __shared__ double lt[kThreads + kRows];
+    if (static_cast<int64_t>(blockIdx.x) < za.nb) {
+        reduce_z_block<P>(za, blockIdx.x, lt, lt + kThreads);
+        return;
+    }
+    reduce_small_round<Outer<T>>(w, wa, tau, blockIdx.x - za.nb, lt);
+}
+
+// As k_finish_body, with the sub-tile ends and block totals formed first
+// from the sub-tile totals of k_reduce_small.
+template <typename Src, int UPQ>
+__device__ __forceinline__ void k_finish_small_body(Src w, WArgs wa, ZArgs za, SharedArgs sh,
+                                                    const double* __restrict__ tau,
+                                                    int32_t* dev_status, double* __restrict__ u_out,
+                                                    int32_t* __restrict__ r, int vec_ok) {
+    static_assert(UPQ >= 1 && UPQ <= kFinishMaxUPQ, "draws per quad");
+    __shared__ __attribute__((aligned(16))) double ssub[kSmallSub];   // tau, then sub-tile ends
+    __shared__ double sbtot[kSmallBlocks];
+    __shared__ double sbeta[kSmallBlocks];
+    __shared__ double szbeta[kFinishMaxZBlocks];
+    __shared__ ScanLds L;
+    const int t = threadIdx.x;
+    const int qi = t & (kQuad - 1);
+    const bool lead = blockIdx.x == 0;
+    const int64_t i0 = static_cast<int64_t>(blockIdx.x) * kUPerWG * UPQ + (t / kQuad);
+    const int nsub_all = static_cast<int>(wa.nb) * kWSubPerBlock;
+    // every independent load first: the sub-tile totals, the spacing block
+    // totals and the in-block spacing prefixes of this quad's draws
+    for (int q = t; q < nsub_all; q += kThreads) ssub[q] = tau[q];
+    ScanIn<> szi;
+    scan_load(za.blk_tot, za.nb, szi);
+    const bool spacings = za.scheme == kSchemeMultinomial;
+    double zrel[UPQ];
+#pragma unroll
+    for (int k = 0; k < UPQ; ++k) {
+        const int64_t i = i0 + static_cast<int64_t>(k) * kUPerWG;
+        zrel[k] = (spacings && i < za.N) ? za.zrel[i] : 0.0;
+    }
+    lds_barrier();
+    // the chain of sub-tile ends of each block, left to right (k_reduce's
+    // order); the block total is its last end
+    if (t < wa.nb) {
+        double c = 0.0;
+        double* e = ssub + t * kWSubPerBlock;
+#pragma unroll 16
+        for (int q = 0; q < kWSubPerBlock; ++q) {
+            c = c + e[q];
+            e[q] = c;
+        }
+        sbtot[t] = c;
+    }
+    lds_barrier();
+    ScanIn<> si[2];
+    scan_load(sbtot, wa.nb, si[0]);
+    si[1] = szi;
+    const ScanOut so[2] = {{sbtot, wa.nb, sbeta, nullptr}, {za.blk_tot, za.nb, szbeta, nullptr}};
+    double tt[2];
+    int bad[2];
+    scan_pair(si, so, L, tt, bad);
+    if (lead) {   // publish the sub-tile ends, scans, totals and status
+        for (int q = t; q < nsub_all; q += kThreads) wa.sub_end[q] = ssub[q];
+        for (int64_t j = t; j < wa.nb; j += kThreads) wa.beta[j] = sbeta[j];
+        for (int64_t j = t; j < za.nb; j += kThreads) za.beta[j] = szbeta[j];
+    }
+    const double tot = tt[0], ztot = tt[1];
+    const int status =
+        (bad[0] || !(tot > 0.0) || !(tot < __builtin_huge_val())) ? kStatusBadWeights : kStatusOk;
+    if (lead && t == 0) {
+        sh.status[0] = status;
+        sh.totals[0] = tot;
+        sh.totals[1] = ztot;
+        if (dev_status) *dev_status = status;
+    }
+    WArgs wl = wa;
+    wl.sub_end = ssub;   // the map reads the sub-tile ends from LDS
+    auto one = [&](int64_t i, double zk) {
+        const int64_t g = i / kZBlock;
+        const double uu = spacings ? uniform_of(zk, i, za.N, (g == 0) ? 0.0 : szbeta[g - 1],
+                                                szbeta[g], ztot)
+                                   : scheme_uniform(za, i);
+        if (u_out && qi == 0) u_out[i] = uu;
+        if (status != kStatusOk) {
+            if (qi == 0) r[i] = -1;
+            return;
+        }
+        const double x = threshold_for(uu, tot);
+        map_quad<Src>(w, wl, sbeta, 1, static_cast<int>(wa.nb), x, i, qi, r, vec_ok);
+    };
+    if constexpr (UPQ == 1) {
+        if (i0 < za.N) one(i0, zrel[0]);
+    } else {
+#pragma unroll 1
+        for (int k = 0; k < UPQ; ++k) {
+            const int64_t i = i0 + static_cast<int64_t>(k) * kUPerWG;
+            if (i >= za.N) break;
+            double zk = zrel[0];
+#pragma unroll
+            for (int q = 1; q < UPQ; ++q) zk = (k == q) ? zrel[q] : zk;
+            one(i, zk);
+        }
+    }
+}
+
+template <typename Tin, int UPQ>
+__global__ __launch_bounds__(kThreads) void k_finish_small(const Tin* __restrict__ w, WArgs wa, ZArgs za, SharedArgs sh, const double* __restrict__ tau, int32_t* dev_status, double* __restrict__ u_out, int32_t* __restrict__ r, int vec_ok) {
+    k_finish_small_body<const Tin*, UPQ>(w, wa, za, sh, tau, dev_status, u_out, r, vec_ok);
+}
+
+template <typename T, int UPQ>
+__global__ __launch_bounds__(kThreads) void k_finish_small_outer(Outer<T> w, WArgs wa, ZArgs za, SharedArgs sh, const double* __restrict__ tau, int32_t* dev_status, double* __restrict__ u_out, int32_t* __restrict__ r, int vec_ok) {
+    k_finish_small_body<Outer<T>, UPQ>(w, wa, za, sh, tau, dev_status, u_out, r, vec_ok);
+}
+
+// ---------------------------------------------------------------------------
 // Stage 3 alone: inverse CMF of sorted u against a given non-decreasing W.
 // Each workgroup takes consecutive uniforms; its first and last uniform are
 // located in the whole of W (a 64-ary search of one wave each, Alg. 2 with a
@@ -2418,6 +2588,62 @@ hipError_t launch_finish(int prec, const WSource& src, const WArgs& wa, const ZA
     } else {
         go(k_finish<double, 1>, k_finish<double, 2>, k_finish<double, 4>,
            static_cast<const double*>(w), vec_ok);
+    }
+    return hipGetLastError();
+}
+
+bool small_fits(const WArgs& wa, const ZArgs& za) {
+    return finish_fits(wa, za) && wa.nb <= kSmallBlocks;
+}
+
+hipError_t launch_reduce_small(int prec, const WSource& src, const WArgs& wa, const ZArgs& za,
+                               double* tau, hipStream_t s) {
+    const dim3 grid(static_cast<unsigned>(za.nb + wa.nb * kWIters));
+    if (src.outer()) {
+        if (prec == kPrecFP32)
+            launch(k_reduce_small_outer<float, kPrecFP32>, grid, dim3(kThreads), 0, s,
+                   src.outer_as<float>(), wa, za, tau);
+        else
+            launch(k_reduce_small_outer<double, kPrecFP64>, grid, dim3(kThreads), 0, s,
+                   src.outer_as<double>(), wa, za, tau);
+    } else if (prec == kPrecFP32) {
+        launch(k_reduce_small<float, kPrecFP32>, grid, dim3(kThreads), 0, s,
+               static_cast<const float*>(src.w), wa, za, tau);
+    } else {
+        launch(k_reduce_small<double, kPrecFP64>, grid, dim3(kThreads), 0, s,
+               static_cast<const double*>(src.w), wa, za, tau);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_finish_small(int prec, const WSource& src, const WArgs& wa, const ZArgs& za,
+                               const SharedArgs& sh, const double* tau, int32_t* dev_status,
+                               double* u_out, int32_t* r, int vec_ok, hipStream_t s) {
+    // a small problem has at most M / 4 < 2^16 sparse draws: one or two per quad
+    const int64_t rounds = (za.N + kUPerWG * kFinishResident - 1) / (kUPerWG * kFinishResident);
+    const int upq = (rounds <= 1) ? 1 : 2;
+    const int64_t per_wg = static_cast<int64_t>(kUPerWG) * upq;
+    const dim3 grid(static_cast<unsigned>((za.N + per_wg - 1) / per_wg));
+    const dim3 block(kThreads);
+    auto go = [&](auto k1, auto k2, auto wsrc, int vec) {
+        if (upq == 1)
+            launch(k1, grid, block, 0, s, wsrc, wa, za, sh, tau, dev_status, u_out, r, vec);
+        else
+            launch(k2, grid, block, 0, s, wsrc, wa, za, sh, tau, dev_status, u_out, r, vec);
+    };
+    if (src.outer()) {
+        if (prec == kPrecFP32)
+            go(k_finish_small_outer<float, 1>, k_finish_small_outer<float, 2>,
+               src.outer_as<float>(), 1);
+        else
+            go(k_finish_small_outer<double, 1>, k_finish_small_outer<double, 2>,
+               src.outer_as<double>(), 1);
+    } else if (prec == kPrecFP32) {
+        go(k_finish_small<float, 1>, k_finish_small<float, 2>, static_cast<const float*>(src.w),
+           vec_ok);
+    } else {
+        go(k_finish_small<double, 1>, k_finish_small<double, 2>,
+           static_cast<const double*>(src.w), vec_ok);
     }
     return hipGetLastError();
 }

@@ -64,6 +64,7 @@ def assert_zero_bins_empty(w, W, r):
 
 CASES = [
     # (M, N, map the fused call takes, blocks per scan thread)
+    (200_000, 3000, "finish", 1),                           # the small path (7 blocks)
     ((1 << 20) + 333, 5000, "finish", 1),
     ((1 << 21) + 3, (1 << 18) + 5, "map_fused", 1),
     (300_000, 200_000, "map_dense", 1),
