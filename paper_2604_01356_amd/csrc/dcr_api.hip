@@ -37,7 +37,7 @@ size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 struct Layout {
     int64_t nwb = 0, nzb = 0;
     size_t status = 0, totals = 0;
-    size_t w_tot = 0, w_beta = 0, w_sub = 0, w_tau = 0;
+    size_t w_tot = 0, w_beta = 0, w_sub = 0;
     size_t z_tot = 0, z_beta = 0, z_buf = 0;
     size_t wide = 0;
     size_t bytes = 0;
@@ -60,10 +60,6 @@ Layout make_layout(int64_t M, int64_t N, int scheme = dcr::kSchemeMultinomial) {
         off = align256(off + sizeof(double) * L.nwb);
         L.w_sub = off;
         off = align256(off + sizeof(double) * L.nwb * kWSubPerBlock);
-        if (L.nwb <= dcr::kSmallBlocks) {   // sub-tile totals of the small path
-            L.w_tau = off;
-            off = align256(off + sizeof(double) * L.nwb * kWSubPerBlock);
-        }
     }
     if (N > 0 && scheme == dcr::kSchemeMultinomial) {
         L.nzb = (N + 1 + kZBlock - 1) / kZBlock;
@@ -461,24 +457,11 @@ dcr_status resample_from(const dcr::WSource& src, int64_t M, int64_t N, uint64_t
     // an outer product has no alignment to honour
     const int vec = ((src.outer() || aligned16(src.w)) ? 1 : 0) | (aligned16(W_opt) ? 2 : 0);
     int32_t* wide = at<int32_t>(ws, L.wide);
-    if (dcr::small_fits(wa, za)) {
-        // a few weight blocks: every round of a block is its own workgroup
-        double* tau = at<double>(ws, L.w_tau);
-        hipError_t e = timed(kKReduce, stream, [&] {
-            return dcr::launch_reduce_small(prec, src, wa, za, tau, stream);
-        });
-        if (e == hipSuccess)
-            e = timed(kKFinish, stream, [&] {
-                return dcr::launch_finish_small(prec, src, wa, za, sh, tau, dev_status, u_opt, r,
-                                                vec, stream);
-            });
-        if (e == hipSuccess && W_opt)
-            e = timed(kKMatW, stream,
-                      [&] { return dcr::launch_materialize_w(prec, src, wa, sh, W_opt, vec, stream); });
-        return hip_status(e);
-    }
-    hipError_t e = timed(kKReduce, stream,
-                         [&] { return dcr::launch_reduce(prec, src, wa, za, vec, stream); });
+    // a few weight blocks: 1024 threads per block, the same sums
+    hipError_t e = timed(kKReduce, stream, [&] {
+        return dcr::small_fits(wa, za) ? dcr::launch_reduce_small(prec, src, wa, za, stream)
+                                       : dcr::launch_reduce(prec, src, wa, za, vec, stream);
+    });
     if (dcr::finish_fits(wa, za)) {
         // block scans, uniforms and map in one launch
         if (e == hipSuccess)

@@ -63,8 +63,7 @@ struct SharedArgs {
 constexpr int kFinishMaxZBlocks = 64;
 
 // Problems of at most this many weight blocks (M <= 2^18) that k_finish
-// takes run k_reduce_small / k_finish_small instead (every round of a block
-// is its own workgroup).
+// takes run k_reduce_small in place of k_reduce.
 constexpr int kSmallBlocks = 8;
 
 // N * kDenseRatio >= M: several uniforms per sub-tile on average, mapped by

@@ -8,9 +8,8 @@
 //   k_materialize_u     sorted uniforms u (stage 2 output)
 //   k_finish            block scans + uniforms + map in one launch (the common
 //                       end-to-end case)
-//   k_reduce_small, k_finish_small
-//                       the same for at most 8 weight blocks, with one
-//                       workgroup per round of sub-tiles in the reduce
+//   k_reduce_small      k_reduce for at most 8 weight blocks: 1024 threads per
+//                       block, so its 8 rounds of loads are in flight at once
 //   k_map_fused         inverse CMF of u against the cumulative weights kept
 //                       implicit (block bases + sub-tile bases + a rescan of one
 //                       256-weight sub-tile), the divide-and-conquer map of
@@ -1480,170 +1479,166 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
 }
 
 // ---------------------------------------------------------------------------
-// Small problems (at most kSmallBlocks weight blocks): the reduce and the
-// finish split the work differently, with the same sums.  A weight block
-// reduced by one workgroup takes 8 dependent rounds of loads, which is the
-// whole time of a call with only a few blocks; here every round of 16
-// sub-tiles is its own workgroup (k_reduce_small), which stores its 16
-// sub-tile totals, and every k_finish_small workgroup runs the chain of
-// sub-tile ends (sigma, left to right) and the block totals in LDS before
-// the scans, then maps with the sub-tile ends read from LDS.
+// Small problems (at most kSmallBlocks weight blocks): k_reduce_small, with
+// the sums of k_reduce.  A weight block reduced by 256 threads takes 8
+// dependent rounds of loads, and a spacing block 16 dependent draws per
+// thread; with only a few blocks that is the whole time of the reduce.  With
+// 1024 threads a weight block has all its loads in flight at once (two lane
+// chunks per thread), and a spacing block four lanes per 16-draw chunk.
 // ---------------------------------------------------------------------------
-constexpr int kSmallSub = kSmallBlocks * kWSubPerBlock;
+constexpr int kSmallThreads = 1024;                   // threads of a k_reduce_small workgroup
+constexpr int kSmallRounds = kSmallThreads / kThreads;  // weight rounds per workgroup
 
-// Round `idx` (block idx / 8, sub-tiles 16 (idx % 8) .. + 15) of the weights:
-// lane-chunk totals left to right, then the 16 sub-tile totals left to right
-// into tau (NaN for a sub-tile holding a negative weight; NaN and infinity
-// reach it through the sums).  All threads call it.
-template <typename Src>
-__device__ __forceinline__ void reduce_small_round(Src w, const WArgs& wa, double* __restrict__ tau,
-                                                   int64_t idx, double* lane_tot) {
-    using Elem = typename SrcElem<Src>::type;
+// Spacing block g by 1024 threads (reduce_z_block's sums, four times the
+// threads): lane qi of quad c takes draws 4qi .. 4qi+3 of lane chunk c, and
+// the chunk's running sum passes from lane to lane in draw order, so every
+// prefix is the same left-to-right sum.  All threads call it.
+template <int P>
+__device__ __forceinline__ void reduce_z_block_quads(const ZArgs& za, int64_t g, double* lane_tot,
+                                                     double* sub_tot) {
     const int t = threadIdx.x;
-    const int row = t / kRowLanes;
-    const int lane = t % kRowLanes;
-    const int64_t b = idx / kWIters;
-    const int s = static_cast<int>(idx % kWIters) * kRows + row;
-    const int64_t j0 = b * kWBlock + static_cast<int64_t>(s) * kSub + lane * kLane;
-    const RawChunk<Elem> rc = src_raw_n(w, j0, clamp_count(wa.M - j0, kLane));
-    Elem mn = rc.raw(0);
-    const double tl = raw_sum<Elem>(rc, mn);
-    lane_tot[t] = (mn < static_cast<Elem>(0)) ? __builtin_nan("") : tl;
-    lds_barrier();
-    if (lane == 0) {
-        const double* p = lane_tot + row * kRowLanes;
-        double c = p[0];
-#pragma unroll
-        for (int l = 1; l < kRowLanes; ++l) c = c + p[l];
-        tau[b * kWSubPerBlock + s] = c;
-    }
-}
-
-template <typename T, int P>
-__global__ __launch_bounds__(kThreads) void k_reduce_small(const T* __restrict__ w, WArgs wa, ZArgs za,
-                                                          double* __restrict__ tau) {
-    __shared__ double lt[kThreads + kRows];
-    if (static_cast<int64_t>(blockIdx.x) < za.nb) {
-        reduce_z_block<P>(za, blockIdx.x, lt, lt + kThreads);
-        return;
-    }
-    reduce_small_round<const T*>(w, wa, tau, blockIdx.x - za.nb, lt);
-}
-
-template <typename T, int P>
-__global__ __launch_bounds__(kThreads) void k_reduce_small_outer(Outer<T> w, WArgs wa, ZArgs za,
-                                                                double* __restrict__ tau) {
-    __shared__ double lt[kThreads + kRows];
-    if (static_cast<int64_t>(blockIdx.x) < za.nb) {
-        reduce_z_block<P>(za, blockIdx.x, lt, lt + kThreads);
-        return;
-    }
-    reduce_small_round<Outer<T>>(w, wa, tau, blockIdx.x - za.nb, lt);
-}
-
-// As k_finish_body, with the sub-tile ends and block totals formed first
-// from the sub-tile totals of k_reduce_small.
-template <typename Src, int UPQ>
-__device__ __forceinline__ void k_finish_small_body(Src w, WArgs wa, ZArgs za, SharedArgs sh,
-                                                    const double* __restrict__ tau,
-                                                    int32_t* dev_status, double* __restrict__ u_out,
-                                                    int32_t* __restrict__ r, int vec_ok) {
-    static_assert(UPQ >= 1 && UPQ <= kFinishMaxUPQ, "draws per quad");
-    __shared__ __attribute__((aligned(16))) double ssub[kSmallSub];   // tau, then sub-tile ends
-    __shared__ double sbtot[kSmallBlocks];
-    __shared__ double sbeta[kSmallBlocks];
-    __shared__ double szbeta[kFinishMaxZBlocks];
-    __shared__ ScanLds L;
-    const int t = threadIdx.x;
+    const int c = t >> 2;   // lane chunk of the block (the thread of the 256-thread layout)
     const int qi = t & (kQuad - 1);
-    const bool lead = blockIdx.x == 0;
-    const int64_t i0 = static_cast<int64_t>(blockIdx.x) * kUPerWG * UPQ + (t / kQuad);
-    const int nsub_all = static_cast<int>(wa.nb) * kWSubPerBlock;
-    // every independent load first: the sub-tile totals, the spacing block
-    // totals and the in-block spacing prefixes of this quad's draws
-    for (int q = t; q < nsub_all; q += kThreads) ssub[q] = tau[q];
-    ScanIn<> szi;
-    scan_load(za.blk_tot, za.nb, szi);
-    const bool spacings = za.scheme == kSchemeMultinomial;
-    double zrel[UPQ];
+    const int row = c / kRowLanes;
+    const int lane = c % kRowLanes;
+    const int64_t i0 = g * kZBlock + static_cast<int64_t>(c) * kLane + 4 * qi;
+    const int nv = clamp_count(za.N + 1 - i0, 4);
+    double x[4];
 #pragma unroll
-    for (int k = 0; k < UPQ; ++k) {
-        const int64_t i = i0 + static_cast<int64_t>(k) * kUPerWG;
-        zrel[k] = (spacings && i < za.N) ? za.zrel[i] : 0.0;
+    for (int k = 0; k < 4; k += 2) {
+        double ze = 0.0, zo = 0.0;
+        if (k < nv) spacing_pair<P>(static_cast<uint64_t>(i0 + k) >> 1, za.seed, za.stream, ze, zo);
+        x[k] = (k < nv) ? ze : 0.0;
+        x[k + 1] = (k + 1 < nv) ? zo : 0.0;
     }
-    lds_barrier();
-    // the chain of sub-tile ends of each block, left to right (k_reduce's
-    // order); the block total is its last end
-    if (t < wa.nb) {
-        double c = 0.0;
-        double* e = ssub + t * kWSubPerBlock;
-#pragma unroll 16
-        for (int q = 0; q < kWSubPerBlock; ++q) {
-            c = c + e[q];
-            e[q] = c;
+    double p[4];
+    double run = 0.0;   // the chunk's sum before lane ph's draws, in every lane
+#pragma unroll
+    for (int ph = 0; ph < kQuad; ++ph) {
+        double a[4];
+        a[0] = (ph == 0) ? x[0] : run + x[0];
+#pragma unroll
+        for (int k = 1; k < 4; ++k) a[k] = a[k - 1] + x[k];
+        if (qi == ph) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) p[k] = a[k];
         }
-        sbtot[t] = c;
+        run = quad_bcast(a[3], ph);
     }
+    if (qi == 0) lane_tot[c] = run;   // the chunk total
     lds_barrier();
-    ScanIn<> si[2];
-    scan_load(sbtot, wa.nb, si[0]);
-    si[1] = szi;
-    const ScanOut so[2] = {{sbtot, wa.nb, sbeta, nullptr}, {za.blk_tot, za.nb, szbeta, nullptr}};
-    double tt[2];
-    int bad[2];
-    scan_pair(si, so, L, tt, bad);
-    if (lead) {   // publish the sub-tile ends, scans, totals and status
-        for (int q = t; q < nsub_all; q += kThreads) wa.sub_end[q] = ssub[q];
-        for (int64_t j = t; j < wa.nb; j += kThreads) wa.beta[j] = sbeta[j];
-        for (int64_t j = t; j < za.nb; j += kThreads) za.beta[j] = szbeta[j];
+    double lv[kRowLanes];
+#pragma unroll
+    for (int k = 0; k < kRowLanes; ++k) lv[k] = lane_tot[row * kRowLanes + k];
+    double cb = 0.0;
+#pragma unroll
+    for (int k = 0; k < kRowLanes; ++k)
+        if (k < lane) cb = cb + lv[k];
+    if (lane == kRowLanes - 1 && qi == 0) sub_tot[row] = cb + lv[kRowLanes - 1];
+    lds_barrier();
+    double rv[kRows];
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) rv[k] = sub_tot[k];
+    double sigma = 0.0, total = 0.0;
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+        if (k < row) sigma = sigma + rv[k];
+        total = total + rv[k];
     }
-    const double tot = tt[0], ztot = tt[1];
-    const int status =
-        (bad[0] || !(tot > 0.0) || !(tot < __builtin_huge_val())) ? kStatusBadWeights : kStatusOk;
-    if (lead && t == 0) {
-        sh.status[0] = status;
-        sh.totals[0] = tot;
-        sh.totals[1] = ztot;
-        if (dev_status) *dev_status = status;
-    }
-    WArgs wl = wa;
-    wl.sub_end = ssub;   // the map reads the sub-tile ends from LDS
-    auto one = [&](int64_t i, double zk) {
-        const int64_t g = i / kZBlock;
-        const double uu = spacings ? uniform_of(zk, i, za.N, (g == 0) ? 0.0 : szbeta[g - 1],
-                                                szbeta[g], ztot)
-                                   : scheme_uniform(za, i);
-        if (u_out && qi == 0) u_out[i] = uu;
-        if (status != kStatusOk) {
-            if (qi == 0) r[i] = -1;
-            return;
-        }
-        const double x = threshold_for(uu, tot);
-        map_quad<Src>(w, wl, sbeta, 1, static_cast<int>(wa.nb), x, i, qi, r, vec_ok);
-    };
-    if constexpr (UPQ == 1) {
-        if (i0 < za.N) one(i0, zrel[0]);
+    double zr[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) zr[k] = sigma + (cb + p[k]);
+    if (nv == 4) {
+        f64x2* q = reinterpret_cast<f64x2*>(za.zrel + i0);
+        q[0] = f64x2{zr[0], zr[1]};
+        q[1] = f64x2{zr[2], zr[3]};
     } else {
-#pragma unroll 1
-        for (int k = 0; k < UPQ; ++k) {
-            const int64_t i = i0 + static_cast<int64_t>(k) * kUPerWG;
-            if (i >= za.N) break;
-            double zk = zrel[0];
+        for (int k = 0; k < nv; ++k) za.zrel[i0 + k] = zr[k];
+    }
+    if (t == 0) za.blk_tot[g] = total;
+}
+
+// Weight block b by 1024 threads: thread (q, row, lane) of the 256-thread
+// layout q = t / 256 sums the lane chunks of rounds q and q + 4, both loaded
+// at once; then k_reduce's epilogue (sub-tile totals, the chain of sub-tile
+// ends, the block total; NaN for a block holding an inadmissible weight).
+// All threads call it; lds holds 2048 + 256 doubles.
+template <typename Src>
+__device__ __forceinline__ void reduce_w_block_wide(Src w, const WArgs& wa, int64_t b,
+                                                    double* lds) {
+    using Elem = typename SrcElem<Src>::type;
+    double* lane_tot = lds;                              // [8][256]
+    double* sub_tot = lds + kWIters * kThreads;          // [128]
+    double* sub_end = sub_tot + kWSubPerBlock;           // [128]
+    const int t = threadIdx.x;
+    const int tr = t % kThreads;
+    const int q = t / kThreads;
+    const int row = tr / kRowLanes;
+    const int lane = tr % kRowLanes;
+    const int64_t j0 = b * kWBlock + static_cast<int64_t>(q * kRows + row) * kSub + lane * kLane;
+    const int64_t j1 = j0 + static_cast<int64_t>(kSmallRounds) * kRows * kSub;
+    const RawChunk<Elem> r0 = src_raw_n(w, j0, clamp_count(wa.M - j0, kLane));
+    const RawChunk<Elem> r1 = src_raw_n(w, j1, clamp_count(wa.M - j1, kLane));
+    Elem mn = r0.raw(0);
+    const double t0 = raw_sum<Elem>(r0, mn);
+    const double t1 = raw_sum<Elem>(r1, mn);
+    const int bad = block_any((mn < static_cast<Elem>(0)) ? 1 : 0);
+    lane_tot[q * kThreads + tr] = t0;
+    lane_tot[(q + kSmallRounds) * kThreads + tr] = t1;
+    lds_barrier();
+    if (t < kWSubPerBlock) {   // sub-tile 16 it + r: the 16 lane totals left to right
+        const int it = t / kRows;
+        const int r = t % kRows;
+        const double* p = lane_tot + it * kThreads + r * kRowLanes;
+        double lv[kRowLanes];
 #pragma unroll
-            for (int q = 1; q < UPQ; ++q) zk = (k == q) ? zrel[q] : zk;
-            one(i, zk);
+        for (int l = 0; l < kRowLanes; ++l) lv[l] = p[l];
+        double c = lv[0];
+#pragma unroll
+        for (int l = 1; l < kRowLanes; ++l) c = c + lv[l];
+        sub_tot[t] = c;
+    }
+    lds_barrier();
+    if (t == 0) {
+        double c = 0.0;
+        for (int q0 = 0; q0 < kWSubPerBlock; q0 += 16) {
+            double v[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) v[k] = sub_tot[q0 + k];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                c = c + v[k];
+                sub_end[q0 + k] = c;
+            }
         }
+    }
+    lds_barrier();
+    if (t < kWSubPerBlock) wa.sub_end[b * kWSubPerBlock + t] = sub_end[t];
+    if (t == 0) {
+        const double tot = sub_end[kWSubPerBlock - 1];
+        wa.blk_tot[b] = (bad || !(tot < __builtin_huge_val())) ? __builtin_nan("") : tot;
     }
 }
 
-template <typename Tin, int UPQ>
-__global__ __launch_bounds__(kThreads) void k_finish_small(const Tin* __restrict__ w, WArgs wa, ZArgs za, SharedArgs sh, const double* __restrict__ tau, int32_t* dev_status, double* __restrict__ u_out, int32_t* __restrict__ r, int vec_ok) {
-    k_finish_small_body<const Tin*, UPQ>(w, wa, za, sh, tau, dev_status, u_out, r, vec_ok);
+template <typename T, int P>
+__global__ __launch_bounds__(kSmallThreads) void k_reduce_small(const T* __restrict__ w, WArgs wa,
+                                                               ZArgs za) {
+    __shared__ double lds[kWIters * kThreads + 2 * kWSubPerBlock];
+    if (static_cast<int64_t>(blockIdx.x) < za.nb) {
+        reduce_z_block_quads<P>(za, blockIdx.x, lds, lds + kSmallThreads);
+        return;
+    }
+    reduce_w_block_wide<const T*>(w, wa, blockIdx.x - za.nb, lds);
 }
 
-template <typename T, int UPQ>
-__global__ __launch_bounds__(kThreads) void k_finish_small_outer(Outer<T> w, WArgs wa, ZArgs za, SharedArgs sh, const double* __restrict__ tau, int32_t* dev_status, double* __restrict__ u_out, int32_t* __restrict__ r, int vec_ok) {
-    k_finish_small_body<Outer<T>, UPQ>(w, wa, za, sh, tau, dev_status, u_out, r, vec_ok);
+template <typename T, int P>
+__global__ __launch_bounds__(kSmallThreads) void k_reduce_small_outer(Outer<T> w, WArgs wa, ZArgs za) {
+    __shared__ double lds[kWIters * kThreads + 2 * kWSubPerBlock];
+    if (static_cast<int64_t>(blockIdx.x) < za.nb) {
+        reduce_z_block_quads<P>(za, blockIdx.x, lds, lds + kSmallThreads);
+        return;
+    }
+    reduce_w_block_wide<Outer<T>>(w, wa, blockIdx.x - za.nb, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -2597,53 +2592,22 @@ bool small_fits(const WArgs& wa, const ZArgs& za) {
 }
 
 hipError_t launch_reduce_small(int prec, const WSource& src, const WArgs& wa, const ZArgs& za,
-                               double* tau, hipStream_t s) {
-    const dim3 grid(static_cast<unsigned>(za.nb + wa.nb * kWIters));
+                               hipStream_t s) {
+    const dim3 grid(static_cast<unsigned>(za.nb + wa.nb));
+    const dim3 block(kSmallThreads);
     if (src.outer()) {
         if (prec == kPrecFP32)
-            launch(k_reduce_small_outer<float, kPrecFP32>, grid, dim3(kThreads), 0, s,
-                   src.outer_as<float>(), wa, za, tau);
+            launch(k_reduce_small_outer<float, kPrecFP32>, grid, block, 0, s,
+                   src.outer_as<float>(), wa, za);
         else
-            launch(k_reduce_small_outer<double, kPrecFP64>, grid, dim3(kThreads), 0, s,
-                   src.outer_as<double>(), wa, za, tau);
+            launch(k_reduce_small_outer<double, kPrecFP64>, grid, block, 0, s,
+                   src.outer_as<double>(), wa, za);
     } else if (prec == kPrecFP32) {
-        launch(k_reduce_small<float, kPrecFP32>, grid, dim3(kThreads), 0, s,
-               static_cast<const float*>(src.w), wa, za, tau);
+        launch(k_reduce_small<float, kPrecFP32>, grid, block, 0, s,
+               static_cast<const float*>(src.w), wa, za);
     } else {
-        launch(k_reduce_small<double, kPrecFP64>, grid, dim3(kThreads), 0, s,
-               static_cast<const double*>(src.w), wa, za, tau);
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_finish_small(int prec, const WSource& src, const WArgs& wa, const ZArgs& za,
-                               const SharedArgs& sh, const double* tau, int32_t* dev_status,
-                               double* u_out, int32_t* r, int vec_ok, hipStream_t s) {
-    // a small problem has at most M / 4 < 2^16 sparse draws: one or two per quad
-    const int64_t rounds = (za.N + kUPerWG * kFinishResident - 1) / (kUPerWG * kFinishResident);
-    const int upq = (rounds <= 1) ? 1 : 2;
-    const int64_t per_wg = static_cast<int64_t>(kUPerWG) * upq;
-    const dim3 grid(static_cast<unsigned>((za.N + per_wg - 1) / per_wg));
-    const dim3 block(kThreads);
-    auto go = [&](auto k1, auto k2, auto wsrc, int vec) {
-        if (upq == 1)
-            launch(k1, grid, block, 0, s, wsrc, wa, za, sh, tau, dev_status, u_out, r, vec);
-        else
-            launch(k2, grid, block, 0, s, wsrc, wa, za, sh, tau, dev_status, u_out, r, vec);
-    };
-    if (src.outer()) {
-        if (prec == kPrecFP32)
-            go(k_finish_small_outer<float, 1>, k_finish_small_outer<float, 2>,
-               src.outer_as<float>(), 1);
-        else
-            go(k_finish_small_outer<double, 1>, k_finish_small_outer<double, 2>,
-               src.outer_as<double>(), 1);
-    } else if (prec == kPrecFP32) {
-        go(k_finish_small<float, 1>, k_finish_small<float, 2>, static_cast<const float*>(src.w),
-           vec_ok);
-    } else {
-        go(k_finish_small<double, 1>, k_finish_small<double, 2>,
-           static_cast<const double*>(src.w), vec_ok);
+        launch(k_reduce_small<double, kPrecFP64>, grid, block, 0, s,
+               static_cast<const double*>(src.w), wa, za);
     }
     return hipGetLastError();
 }

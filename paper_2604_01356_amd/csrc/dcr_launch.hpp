@@ -55,15 +55,11 @@ hipError_t launch_carries(const WArgs& wa, const ZArgs& za, const SharedArgs& sh
 hipError_t launch_finish(int prec, const WSource& src, const WArgs& wa, const ZArgs& za,
                          const SharedArgs& sh, int32_t* dev_status, double* u_out, int32_t* r,
                          int vec_ok, hipStream_t s);
-// Problems of at most 8 weight blocks that the finishing launch takes: the
-// reduce splits every block into its 8 rounds (sub-tile totals into tau,
-// nb * 128 doubles), the finish forms the sub-tile ends and block totals.
+// Problems of at most 8 weight blocks that the finishing launch takes:
+// k_reduce_small (1024 threads per block) in place of k_reduce.
 bool small_fits(const WArgs& wa, const ZArgs& za);
 hipError_t launch_reduce_small(int prec, const WSource& src, const WArgs& wa, const ZArgs& za,
-                               double* tau, hipStream_t s);
-hipError_t launch_finish_small(int prec, const WSource& src, const WArgs& wa, const ZArgs& za,
-                               const SharedArgs& sh, const double* tau, int32_t* dev_status,
-                               double* u_out, int32_t* r, int vec_ok, hipStream_t s);
+                               hipStream_t s);
 hipError_t launch_materialize_w(int prec, const WSource& src, const WArgs& wa, const SharedArgs& sh,
                                 double* W, int vec_ok, hipStream_t s);
 hipError_t launch_materialize_u(const ZArgs& za, const SharedArgs& sh, double* u, hipStream_t s);
