@@ -176,7 +176,8 @@ constexpr int kChunks[3] = {256, 512, 1024};   // draws per map workgroup the li
 
 struct BatchLayout {
     int64_t wt_cap = 0, zt_cap = 0, mc_cap = 0;
-    size_t head = 0, wt_base = 0, zt_base = 0, mc_base = 0, seg_status = 0, seg_totals = 0;
+    size_t head = 0, wt_base = 0, zt_base = 0, mc_base = 0, mc_seg = 0, seg_status = 0,
+           seg_totals = 0;
     size_t wt_tot = 0, wt_beta = 0, wt_sub = 0, wt_chunk = 0, zt_tot = 0, zt_beta = 0, zrel = 0;
     size_t bytes = 0;
 };
@@ -196,6 +197,7 @@ BatchLayout make_batch_layout(int64_t B, int64_t sumM, int64_t sumN) {
     L.wt_base = take(sizeof(int64_t) * (B + 1));
     L.zt_base = take(sizeof(int64_t) * (B + 1));
     L.mc_base = take(sizeof(int64_t) * (B + 1));
+    L.mc_seg = take(sizeof(int32_t) * L.mc_cap);
     L.seg_status = take(sizeof(int32_t) * B);
     L.seg_totals = take(sizeof(double) * 2 * B);
     L.wt_tot = take(sizeof(double) * L.wt_cap);
@@ -230,6 +232,7 @@ dcr::BatchArgs batch_args(const BatchLayout& L, void* ws, const int64_t* w_off,
     ba.wt_base = at<int64_t>(ws, L.wt_base);
     ba.zt_base = at<int64_t>(ws, L.zt_base);
     ba.mc_base = at<int64_t>(ws, L.mc_base);
+    ba.mc_seg = at<int32_t>(ws, L.mc_seg);
     ba.head = at<int32_t>(ws, L.head);
     ba.wt_tot = at<double>(ws, L.wt_tot);
     ba.wt_beta = at<double>(ws, L.wt_beta);

@@ -86,6 +86,7 @@ struct BatchArgs {
     int64_t* wt_base;       // [B+1] first weight block of each filter (k_batch_plan)
     int64_t* zt_base;       // [B+1] first spacing block
     int64_t* mc_base;       // [B+1] first map chunk (`chunk` draws)
+    int32_t* mc_seg;        // [mc_cap] filter of each map chunk (k_carries_batched)
     int32_t* head;          // [0] plan status, [1] batch status
     double* wt_tot;         // [wt_cap] weight-block totals
     double* wt_beta;        // [wt_cap] weight-block ends (per filter)

@@ -1971,6 +1971,9 @@ __global__ __launch_bounds__(kScanThreads) void k_carries_batched(BatchArgs ba) 
     // the sums are the same either way
     carries_body<kBatchScanRegs>(seg_wargs(ba, b), seg_zargs(ba, b), sh, nullptr, nullptr, L);
     if (threadIdx.x == 0 && sh.status[0] != kStatusOk) atomicMax(ba.head + 1, kStatusBadWeights);
+    // the filter of each of its map chunks, for the map's lookup
+    const int64_t m0 = ba.mc_base[b], m1 = ba.mc_base[b + 1];
+    for (int64_t c = m0 + threadIdx.x; c < m1; c += kScanThreads) ba.mc_seg[c] = b;
 }
 
 // ---------------------------------------------------------------------------
@@ -2060,19 +2063,20 @@ __device__ void map_seg_chunk(const Tin* __restrict__ w, const WArgs& wa, const 
         zlo[k] = (g == 0) ? 0.0 : za.beta[g - 1];
         zhi[k] = za.beta[g];
     }
-    if (status != kStatusOk) {
-        for (int k = 0; k < kSegPer; ++k) {
-            const int pos = t + k * kThreads;
-            if (pos < nu) r[i0 + pos] = -1;
-        }
-        return;
-    }
+    // the block ends in the same round trip (in range whatever the status)
     const int64_t nb = wa.nb;
     const int64_t kstride = (nb + kSegBetaLds - 1) / kSegBetaLds;
     const int ns = static_cast<int>((nb + kstride - 1) / kstride);
     for (int q = t; q < ns; q += kThreads) {
         const int64_t b = (static_cast<int64_t>(q) + 1) * kstride - 1;
         L.sbeta[q] = wa.beta[b < nb ? b : nb - 1];
+    }
+    if (status != kStatusOk) {
+        for (int k = 0; k < kSegPer; ++k) {
+            const int pos = t + k * kThreads;
+            if (pos < nu) r[i0 + pos] = -1;
+        }
+        return;
     }
     // block end beta_b and the previous end, from LDS when every end is there
     auto beta_end = [&](int64_t b) { return (kstride == 1) ? L.sbeta[b] : wa.beta[b]; };
@@ -2144,13 +2148,43 @@ __device__ void map_seg_chunk(const Tin* __restrict__ w, const WArgs& wa, const 
             nsub[k] = static_cast<int>((blen + kSub - 1) / kSub);
             cnt[k] = 0;
         }
-        // count of sub-tile ends below x among the first nsub-1, in lock step
-        for (int step = kWSubPerBlock / 2; step >= 1; step >>= 1) {
+        // count of sub-tile ends below x among the first nsub-1, in lock step:
+        // a bisection in LDS when the chunk's blocks are staged; otherwise two
+        // rounds of independent loads from memory (the last end of each group
+        // of 16 sub-tiles, then the 16 ends of the group holding the answer)
+        if (staged) {
+            for (int step = kWSubPerBlock / 2; step >= 1; step >>= 1) {
 #pragma unroll
-            for (int k = 0; k < kSegPer; ++k)
-                if (cnt[k] + step <= nsub[k] - 1 &&
-                    block_end_at(sigma_of(bk[k], cnt[k] + step), bx[k], bb[k], bn[k]) < xs[k])
-                    cnt[k] += step;
+                for (int k = 0; k < kSegPer; ++k)
+                    if (cnt[k] + step <= nsub[k] - 1 &&
+                        block_end_at(sigma_of(bk[k], cnt[k] + step), bx[k], bb[k], bn[k]) < xs[k])
+                        cnt[k] += step;
+            }
+        } else {
+            constexpr int kGroup = 16;
+            constexpr int kGroups = kWSubPerBlock / kGroup;
+#pragma unroll 1
+            for (int k = 0; k < kSegPer; ++k) {   // one draw at a time (few registers)
+                const double* se = wa.sub_end + bk[k] * kWSubPerBlock;
+                double e[kGroups];
+#pragma unroll
+                for (int g = 0; g < kGroups; ++g) e[g] = se[g * kGroup + kGroup - 1];
+                int c1 = 0;
+#pragma unroll
+                for (int g = 0; g < kGroups; ++g)
+                    c1 += (g * kGroup + kGroup - 1 < nsub[k] - 1 &&
+                           block_end_at(e[g], bx[k], bb[k], bn[k]) < xs[k]) ? 1 : 0;
+                const int g0 = (c1 < kGroups) ? c1 : kGroups - 1;
+                double f[kGroup];
+#pragma unroll
+                for (int q = 0; q < kGroup; ++q) f[q] = se[g0 * kGroup + q];
+                int c2 = 0;
+#pragma unroll
+                for (int q = 0; q < kGroup; ++q)
+                    c2 += (c1 * kGroup + q < nsub[k] - 1 &&
+                           block_end_at(f[q], bx[k], bb[k], bn[k]) < xs[k]) ? 1 : 0;
+                cnt[k] = c1 * kGroup + ((c1 < kGroups) ? c2 : 0);
+            }
         }
 #pragma unroll
         for (int k = 0; k < kSegPer; ++k) {
@@ -2326,7 +2360,9 @@ __global__ __launch_bounds__(kThreads) void k_map_batched(const Tin* __restrict_
     const int plan = ba.head[0];
     const int64_t nchunks = ba.mc_base[ba.B];
     const int64_t c = blockIdx.x;
-    const int b = find_segment(ba.mc_base, ba.B, c);
+    // written by k_carries_batched for every chunk when the plan succeeded;
+    // read only then, and only for c < nchunks
+    const int b = ba.mc_seg[c < ba.mc_cap ? c : 0];
     if (blockIdx.x == 0 && threadIdx.x == 0 && dev_status)
         *dev_status = (plan != kStatusOk) ? plan : ba.head[1];
     if (plan != kStatusOk) return;
