@@ -26,7 +26,8 @@
  *     on the device: then `*dev_status` (if not NULL) receives
  *     DCR_ERR_BAD_WEIGHTS, every r_i is set to -1 and W is not meaningful;
  *     otherwise `*dev_status` receives DCR_OK.  A failed HIP launch returns
- *     DCR_ERR_HIP.
+ *     DCR_ERR_HIP (the status of the library's own launches, not an earlier,
+ *     unrelated HIP error).
  *   - Sizes: 1 <= M <= 2^31 - 1 and 0 <= N <= 2^31 - 2; N = 0 draws nothing.
  *     N > M is allowed.
  *   - Randomness: draw i of (seed, stream_id) comes from Philox4x32-10
@@ -312,7 +313,9 @@ dcr_status dcr_resample_noalloc(const void* w, int64_t M, int64_t N, uint64_t se
  * kernel kind k (see dcr_profile_kind_name), stores
  * the launch count in counts[k] and the summed milliseconds in ms[k]
  * (arrays of n_kinds entries, host memory).  Kinds beyond n_kinds are dropped.
- * Not thread safe; meant for one measuring thread. */
+ * Profiling is per host thread: it records the launches made by the thread that
+ * called dcr_profile_begin, and other threads' calls are neither recorded nor
+ * affected. */
 dcr_status dcr_profile_begin(int32_t cap);
 dcr_status dcr_profile_end(int32_t n_kinds, int64_t* counts, double* ms);
 int32_t dcr_profile_kind_count(void);

@@ -16,7 +16,7 @@
 #include "dcr_launch.hpp"
 
 namespace dcr {
-LaunchEvents g_launch_events;
+thread_local LaunchEvents g_launch_events;
 }
 
 namespace {
@@ -137,7 +137,7 @@ struct Profiler {
     std::vector<hipEvent_t> ev;
     std::vector<int> kind;
 };
-Profiler g_prof;
+thread_local Profiler g_prof;   // each host thread profiles its own launches
 
 // Runs one launcher; while profiling, its kernel records its own start and
 // end into the next pair of events (a launcher that launches nothing, e.g. for

@@ -27,6 +27,7 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <tuple>
 #include <type_traits>
 
 #include "dcr_device.hpp"
@@ -2421,12 +2422,32 @@ __global__ __launch_bounds__(kThreads) void k_stream_copy(const f32x4* __restric
 // Host-side launchers
 // ---------------------------------------------------------------------------
 // Every kernel launch of the library goes through here: the launch records
-// its own start and end into the timing events when they are set.
-template <typename K, typename... A>
-static void launch(K kernel, dim3 grid, dim3 block, uint32_t shmem, hipStream_t s, A... args) {
-    hipExtLaunchKernelGGL(kernel, grid, block, shmem, s, g_launch_events.start,
-                          g_launch_events.stop, 0, args...);
+// its own start and end into the timing events when they are set.  The status
+// of the launch itself (not an earlier, unrelated HIP error) is kept for the
+// launcher to return: the first failure since the last take_launch_status().
+thread_local hipError_t g_launch_status = hipSuccess;
+
+template <typename... P, typename... A>
+static void launch(void (*kernel)(P...), dim3 grid, dim3 block, uint32_t shmem, hipStream_t s,
+                   A... args) {
+    static_assert(sizeof...(P) == sizeof...(A), "one value per kernel parameter");
+    std::tuple<P...> vals(args...);   // each value as the parameter's own type
+    void* argv[sizeof...(P)];
+    std::apply([&argv](auto&... v) {
+        int k = 0;
+        ((argv[k++] = static_cast<void*>(&v)), ...);
+    }, vals);
+    const hipError_t e =
+        hipExtLaunchKernel(reinterpret_cast<const void*>(kernel), grid, block, argv, shmem, s,
+                           g_launch_events.start, g_launch_events.stop, 0);
+    if (e != hipSuccess && g_launch_status == hipSuccess) g_launch_status = e;
     ++g_launch_events.launches;
+}
+
+static hipError_t take_launch_status() {
+    const hipError_t e = g_launch_status;
+    g_launch_status = hipSuccess;
+    return e;
 }
 
 template <typename Tin, int P>
@@ -2436,7 +2457,7 @@ static hipError_t launch_reduce_t(const void* w, const WArgs& wa, const ZArgs& z
     if (grid <= 0) return hipSuccess;
     launch((k_reduce<Tin, P>), dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s,
                        static_cast<const Tin*>(w), wa, za, vec_ok);
-    return hipGetLastError();
+    return take_launch_status();
 }
 
 hipError_t launch_reduce(int prec, const WSource& src, const WArgs& wa, const ZArgs& za, int vec_ok,
@@ -2450,7 +2471,7 @@ hipError_t launch_reduce(int prec, const WSource& src, const WArgs& wa, const ZA
         else
             launch(k_reduce_outer<double, kPrecFP64>, dim3(static_cast<unsigned>(grid)),
                    dim3(kThreads), 0, s, src.outer_as<double>(), wa, za);
-        return hipGetLastError();
+        return take_launch_status();
     }
     if (prec == kPrecFP32) return launch_reduce_t<float, kPrecFP32>(src.w, wa, za, vec_ok, s);
     return launch_reduce_t<double, kPrecFP64>(src.w, wa, za, vec_ok, s);
@@ -2460,7 +2481,7 @@ hipError_t launch_carries(const WArgs& wa, const ZArgs& za, const SharedArgs& sh
                           int32_t* dev_status, double* total_out, hipStream_t s) {
     launch(k_carries, dim3(1), dim3(kScanThreads), 0, s, wa, za, sh, dev_status,
                        total_out);
-    return hipGetLastError();
+    return take_launch_status();
 }
 
 hipError_t launch_materialize_w(int prec, const WSource& src, const WArgs& wa, const SharedArgs& sh,
@@ -2481,7 +2502,7 @@ hipError_t launch_materialize_w(int prec, const WSource& src, const WArgs& wa, c
     else
         launch(k_materialize_w<double>, dim3(static_cast<unsigned>(grid)),
                            dim3(kThreads), 0, s, static_cast<const double*>(w), wa, sh, W, vec_ok);
-    return hipGetLastError();
+    return take_launch_status();
 }
 
 hipError_t launch_materialize_u(const ZArgs& za, const SharedArgs& sh, double* u, hipStream_t s) {
@@ -2491,7 +2512,7 @@ hipError_t launch_materialize_u(const ZArgs& za, const SharedArgs& sh, double* u
     const int vec_out = (reinterpret_cast<uintptr_t>(u) % 16) == 0 ? 1 : 0;
     launch(k_materialize_u, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s, za, sh, u,
            vec_out);
-    return hipGetLastError();
+    return take_launch_status();
 }
 
 hipError_t launch_map_fused(int prec, const WSource& src, const WArgs& wa, const ZArgs& za,
@@ -2513,7 +2534,7 @@ hipError_t launch_map_fused(int prec, const WSource& src, const WArgs& wa, const
     else
         launch(k_map_fused<double>, dim3(static_cast<unsigned>(grid)), dim3(kThreads),
                            0, s, static_cast<const double*>(w), wa, za, sh, u_out, r, vec_ok);
-    return hipGetLastError();
+    return take_launch_status();
 }
 
 // Uniforms per dense-map workgroup: about 13/16 of a window's weights' worth
@@ -2552,7 +2573,7 @@ hipError_t launch_map_dense(int prec, const WSource& src, const WArgs& wa, const
     else
         launch(k_map_dense<double>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s,
                static_cast<const double*>(w), wa, za, sh, u_out, r, wide, per);
-    return hipGetLastError();
+    return take_launch_status();
 }
 
 hipError_t launch_map_wide(int prec, const WSource& src, const WArgs& wa, const ZArgs& za,
@@ -2575,7 +2596,7 @@ hipError_t launch_map_wide(int prec, const WSource& src, const WArgs& wa, const 
     else
         launch(k_map_wide<double>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s,
                static_cast<const double*>(w), wa, za, sh, r, wide, vec_ok, per);
-    return hipGetLastError();
+    return take_launch_status();
 }
 
 bool map_is_dense(int64_t M, int64_t N) { return N * kDenseRatio >= M; }
@@ -2620,7 +2641,7 @@ hipError_t launch_finish(int prec, const WSource& src, const WArgs& wa, const ZA
         go(k_finish<double, 1>, k_finish<double, 2>, k_finish<double, 4>,
            static_cast<const double*>(w), vec_ok);
     }
-    return hipGetLastError();
+    return take_launch_status();
 }
 
 bool small_fits(const WArgs& wa, const ZArgs& za) {
@@ -2645,7 +2666,7 @@ hipError_t launch_reduce_small(int prec, const WSource& src, const WArgs& wa, co
         launch(k_reduce_small<double, kPrecFP64>, grid, block, 0, s,
                static_cast<const double*>(src.w), wa, za);
     }
-    return hipGetLastError();
+    return take_launch_status();
 }
 
 hipError_t launch_map_w(const double* W, int64_t M, const double* u, int64_t N, int32_t* r,
@@ -2654,11 +2675,11 @@ hipError_t launch_map_w(const double* W, int64_t M, const double* u, int64_t N, 
     if (map_is_dense(M, N)) {
         launch(k_map_w_dense, dim3(static_cast<unsigned>(dense_chunks(M, N))), dim3(kThreads), 0,
                s, W, M, u, N, r, dense_per_wg(M, N));
-        return hipGetLastError();
+        return take_launch_status();
     }
     const int64_t grid = (N + kThreads - 1) / kThreads;
     launch(k_map_w, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s, W, M, u, N, r);
-    return hipGetLastError();
+    return take_launch_status();
 }
 
 
@@ -2681,12 +2702,12 @@ hipError_t launch_stream_probe(int kind, int unroll, const void* src, void* dst,
         launch_stream_probe_t<8>(kind, src, dst, pieces, grid, s);
     else
         launch_stream_probe_t<4>(kind, src, dst, pieces, grid, s);
-    return hipGetLastError();
+    return take_launch_status();
 }
 
 hipError_t launch_batch_plan(const BatchArgs& ba, int32_t* dev_status, hipStream_t s) {
     launch(k_batch_plan, dim3(1), dim3(kPlanThreads), 0, s, ba, dev_status);
-    return hipGetLastError();
+    return take_launch_status();
 }
 
 hipError_t launch_reduce_batched(int prec, const void* w, const BatchArgs& ba, hipStream_t s) {
@@ -2697,12 +2718,12 @@ hipError_t launch_reduce_batched(int prec, const void* w, const BatchArgs& ba, h
     else
         launch(k_reduce_batched<double, kPrecFP64>, dim3(grid), dim3(kThreads), 0, s,
                static_cast<const double*>(w), ba);
-    return hipGetLastError();
+    return take_launch_status();
 }
 
 hipError_t launch_carries_batched(const BatchArgs& ba, hipStream_t s) {
     launch(k_carries_batched, dim3(static_cast<unsigned>(ba.B)), dim3(kScanThreads), 0, s, ba);
-    return hipGetLastError();
+    return take_launch_status();
 }
 
 template <typename Tin>
@@ -2774,7 +2795,7 @@ hipError_t launch_map_batched(int prec, const void* w, const BatchArgs& ba, int3
         launch_map_batched_t(static_cast<const float*>(w), ba, r, dev_status, s);
     else
         launch_map_batched_t(static_cast<const double*>(w), ba, r, dev_status, s);
-    return hipGetLastError();
+    return take_launch_status();
 }
 
 }  // namespace dcr

@@ -11,13 +11,14 @@ namespace dcr {
 
 // Optional timing of the next kernel launch: when `start` and `stop` are set,
 // the launch records its own start and end into them (hipExtLaunchKernel), so
-// the interval is the kernel alone.  `launches` counts every launch made.
+// the interval is the kernel alone.  `launches` counts every launch made.  One
+// instance per host thread: calls from different threads share no state.
 struct LaunchEvents {
     hipEvent_t start = nullptr;
     hipEvent_t stop = nullptr;
     int64_t launches = 0;
 };
-extern LaunchEvents g_launch_events;
+extern thread_local LaunchEvents g_launch_events;
 
 // Where the weights come from: an array `w` of the precision's type, or
 // (P > 0) the outer product w_j = a[j / P] * b[j % P] of two such arrays.
