@@ -221,15 +221,18 @@ def measure_copy_bw(dcr, torch, dev, reps: int = 10) -> dict:
     res = {"read_gbs": 0.0, "copy_gbs": 0.0}
     for unroll in (4, 8, 16):
         for grid in (1024, 2048, 4096, 8192, 16384):
-            t = med(lambda: dcr.dcr_stream_probe(0, src, dst, grid, unroll))
-            if CALIBRATE_BYTES / t / 1e9 > res["read_gbs"]:
-                res["read_gbs"], res["read_launch"] = CALIBRATE_BYTES / t / 1e9, [grid, unroll]
+            for kind, name in ((0, "grid-stride"), (2, "contiguous runs, non-temporal")):
+                t = med(lambda: dcr.dcr_stream_probe(kind, src, dst, grid, unroll))
+                if CALIBRATE_BYTES / t / 1e9 > res["read_gbs"]:
+                    res["read_gbs"] = CALIBRATE_BYTES / t / 1e9
+                    res["read_launch"] = [name, grid, unroll]
             t = med(lambda: dcr.dcr_stream_probe(1, src, dst, grid, unroll))
             if 2 * CALIBRATE_BYTES / t / 1e9 > res["copy_gbs"]:
                 res["copy_gbs"], res["copy_launch"] = 2 * CALIBRATE_BYTES / t / 1e9, [grid, unroll]
     res["torch_copy_gbs"] = 2 * CALIBRATE_BYTES / med(lambda: dst.copy_(src)) / 1e9
     res["note"] = ("1 GiB: read = bytes read / time, copy = bytes read + written / time; "
-                   f"median of {reps} launches; best [grid, loads in flight] of the sweep")
+                   f"median of {reps} launches; best [pattern, grid, loads in flight] of the "
+                   "sweep")
     del src, dst
     torch.cuda.empty_cache()
     return res

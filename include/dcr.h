@@ -323,8 +323,10 @@ const char* dcr_profile_kind_name(int32_t kind);
 
 /* Bandwidth reference for measurement (not part of the sampling contract):
  * kind 0 streams `bytes` from src (coalesced 16-byte loads, `unroll` = 4, 8
- * or 16 in flight per thread) and writes one float partial sum per workgroup
- * to dst (grid floats); kind 1 copies `bytes` from src to dst.  `grid`
+ * or 16 in flight per thread, grid-stride) and writes one float partial sum
+ * per workgroup to dst (grid floats); kind 2 does the same with one contiguous
+ * run of src per workgroup and non-temporal loads (the access pattern of the
+ * weight stream); kind 1 copies `bytes` from src to dst.  `grid`
  * workgroups of 256 threads.  src and dst 16-byte aligned, bytes a positive
  * multiple of 16; otherwise DCR_ERR_INVALID_ARGUMENT.  Asynchronous on
  * `stream`. */

@@ -654,7 +654,7 @@ dcr_status dcr_profile_end(int32_t n_kinds, int64_t* counts, double* ms) {
 
 dcr_status dcr_stream_probe(int32_t kind, int32_t unroll, const void* src, void* dst,
                             size_t bytes, int32_t grid, hipStream_t stream) {
-    if ((kind != 0 && kind != 1) || !src || !dst || bytes == 0 || (bytes & 15) != 0 || grid < 1)
+    if (kind < 0 || kind > 2 || !src || !dst || bytes == 0 || (bytes & 15) != 0 || grid < 1)
         return DCR_ERR_INVALID_ARGUMENT;
     if (unroll != 4 && unroll != 8 && unroll != 16) return DCR_ERR_INVALID_ARGUMENT;
     if (((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15) != 0)

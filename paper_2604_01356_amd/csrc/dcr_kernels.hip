@@ -217,7 +217,8 @@ __device__ __forceinline__ void reduce_w_block(const Tin* __restrict__ w, const 
                 const float* g0 = src + it * (kWaves * kWaveRoundF32);
 #pragma unroll
                 for (int k = 0; k < kLane / 4; ++k)
-                    __builtin_amdgcn_global_load_lds(g0 + k * 256 + l64 * 4, dst + k * 256, 16, 0, 0);
+                    __builtin_amdgcn_global_load_lds(g0 + k * 256 + l64 * 4, dst + k * 256, 16, 0,
+                                                     kCachePolicyNT);
             };
             float mn = 0.0f;
 #pragma unroll
@@ -259,7 +260,8 @@ __device__ __forceinline__ void reduce_w_block(const Tin* __restrict__ w, const 
                 const float* g0 = src + it * (kWaves * kWaveRoundF32);
 #pragma unroll
                 for (int k = 0; k < kLane / 4; ++k)
-                    __builtin_memcpy(&dst[k], g0 + k * 256 + l64 * 4, sizeof(f32x4));
+                    dst[k] = __builtin_nontemporal_load(
+                        reinterpret_cast<const f32x4_ea*>(g0 + k * 256 + l64 * 4));
             };
 #pragma unroll
             for (int it = 0; it < DEPTH; ++it) fetch(it, ring[it]);
@@ -285,7 +287,9 @@ __device__ __forceinline__ void reduce_w_block(const Tin* __restrict__ w, const 
     }
     if (full && !done) {
         // binary64: lane-strided vector loads (element-aligned), the next
-        // round issued before summing
+        // round issued before summing.  These stay cached: each lane reads its
+        // own 128-byte line in eight pieces, and non-temporal loads would send
+        // every piece to memory (measured 2.5 times slower)
         const Tin* base = w + blk0 + row * kSub + lane * kLane;
         Tin mn = static_cast<Tin>(0);
         RawChunk<Tin> cur = load_raw_any<Tin>(base);
@@ -2403,6 +2407,36 @@ __global__ __launch_bounds__(kThreads) void k_stream_read(const f32x4* __restric
     }
 }
 
+// The pattern of the reduce: every workgroup reads its own contiguous run of
+// `per` pieces (the last one what remains of the n) with non-temporal loads,
+// U in flight per thread.
+template <int U>
+__global__ __launch_bounds__(kThreads) void k_stream_read_blocks(const f32x4* __restrict__ src,
+                                                                int64_t n, int64_t per,
+                                                                float* __restrict__ part) {
+    const int64_t first = static_cast<int64_t>(blockIdx.x) * per;
+    const int64_t lim = (first + per < n) ? per : ((n > first) ? n - first : 0);
+    const f32x4* p = src + first;
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int64_t i = threadIdx.x; i < lim; i += static_cast<int64_t>(kThreads) * U) {
+        f32x4 v[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+            v[k] = (i + k * kThreads < lim) ? __builtin_nontemporal_load(p + i + k * kThreads)
+                                            : f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int k = 0; k < U; ++k) acc += v[k];
+    }
+    __shared__ float red[kThreads];
+    red[threadIdx.x] = acc.x + acc.y + acc.z + acc.w;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float t = 0.f;
+        for (int k = 0; k < kThreads; ++k) t += red[k];
+        part[blockIdx.x] = t;
+    }
+}
+
 template <int U>
 __global__ __launch_bounds__(kThreads) void k_stream_copy(const f32x4* __restrict__ src, int64_t n,
                                                           f32x4* __restrict__ dst) {
@@ -2689,9 +2723,13 @@ static void launch_stream_probe_t(int kind, const void* src, void* dst, int64_t 
     if (kind == 0)
         launch(k_stream_read<U>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s,
                static_cast<const f32x4*>(src), pieces, static_cast<float*>(dst));
-    else
+    else if (kind == 1)
         launch(k_stream_copy<U>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s,
                static_cast<const f32x4*>(src), pieces, static_cast<f32x4*>(dst));
+    else
+        launch(k_stream_read_blocks<U>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s,
+               static_cast<const f32x4*>(src), pieces, (pieces + grid - 1) / grid,
+               static_cast<float*>(dst));
 }
 
 hipError_t launch_stream_probe(int kind, int unroll, const void* src, void* dst, int64_t pieces,

@@ -70,9 +70,10 @@ hipError_t launch_map_fused(int prec, const WSource& src, const WArgs& wa, const
 hipError_t launch_map_w(const double* W, int64_t M, const double* u, int64_t N, int32_t* r,
                         hipStream_t s);
 
-// Streaming read (kind 0: one float partial sum per workgroup into dst) or
-// copy (kind 1) of `pieces` 16-byte pieces, `unroll` (4, 8, 16) loads in
-// flight per thread, for bandwidth reference.
+// Streaming read (kind 0: grid-stride, one float partial sum per workgroup
+// into dst), copy (kind 1), or read of one contiguous run per workgroup with
+// non-temporal loads (kind 2) of `pieces` 16-byte pieces, `unroll` (4, 8, 16)
+// loads in flight per thread, for bandwidth reference.
 hipError_t launch_stream_probe(int kind, int unroll, const void* src, void* dst, int64_t pieces,
                                int grid, hipStream_t s);
 

@@ -18,8 +18,11 @@ def test_stream_probe_copy_and_read():
         dcr.dcr_stream_probe(1, src, dst, 96, unroll)
         part = torch.zeros(96, dtype=torch.float32, device="cuda:0")
         dcr.dcr_stream_probe(0, src, part, 96, unroll)
+        part2 = torch.zeros(96, dtype=torch.float32, device="cuda:0")
+        dcr.dcr_stream_probe(2, src, part2, 96, unroll)   # 96 runs, the last one shorter
         torch.cuda.synchronize()
         assert torch.equal(dst, src)
         assert float(part.double().sum()) == float(src.double().sum())
+        assert float(part2.double().sum()) == float(src.double().sum())
     with pytest.raises(dcr.DcrError):
-        dcr.dcr_stream_probe(2, src, dst, 96)
+        dcr.dcr_stream_probe(3, src, dst, 96)
