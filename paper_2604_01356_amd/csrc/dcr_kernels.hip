@@ -1157,9 +1157,10 @@ __global__ __launch_bounds__(kThreads) void k_map_fused_outer(Outer<T> w, WArgs 
 // them fall in (the split of Alg. 5).  The span is re-summed a window at a
 // time into LDS as normalised cumulative weights (the values of
 // k_materialize_w); then every thread places its own 16 sorted uniforms that
-// end in the window: a search for the first, galloping forward for the
-// others (the merge of Alg. 4, one run of uniforms per thread, so the work is
-// the same for every thread however the weights are spread).  A span wider
+// end in the window (the merge of Alg. 4, one run of uniforms per thread):
+// a table of the window's value buckets narrows each uniform's search to a
+// few entries, and the short bisections of several uniforms run
+// interleaved, so no thread waits on a long chain of LDS reads.  A span wider
 // than 64 sub-tiles is flagged and left to k_map_wide (one quad search per
 // uniform).
 // ---------------------------------------------------------------------------
@@ -1170,64 +1171,123 @@ constexpr int kWinLen = kWinSub * kSub;       // weights per window (= kThreads 
 constexpr int kMaxWin = 4;
 static_assert(kWinLen <= kBetaLds, "the window reuses the block-end stage");
 
+// Bucket index of a window of non-decreasing values: with lo the first value
+// and hi the last, bucket(x) = floor((x - lo) * kBuckets / (hi - lo)) clamped
+// to 0..kBuckets-1 (0 everywhere when the window has no width).  Every step
+// (the subtraction, the product with a non-negative factor, the truncation
+// and the clamp) is monotone in x, so bucket(sw[i]) < bucket(v) implies
+// sw[i] < v, and bucket(sw[i]) > bucket(v) implies sw[i] > v.
+constexpr int kBuckets = 2048;
+constexpr int kPlaceGroup = 4;   // draws whose searches are interleaved
+
+struct WinBuckets {
+    double lo;
+    double scale;
+    __device__ __forceinline__ int of(double x) const {
+        const double d = (x - lo) * scale;
+        if (d >= static_cast<double>(kBuckets - 1)) return kBuckets - 1;
+        return d > 0.0 ? static_cast<int>(d) : 0;
+    }
+};
+
+// Fills tb[0..kBuckets]: tb[b] is the first of the window's first n = nwin-1
+// entries whose bucket is >= b, or n if there is none.  Entry i writes the
+// buckets (bucket(i-1), bucket(i)]; with -1 before the first entry and
+// kBuckets after the last these runs cover every b, so each tb[b] is written
+// and holds an index in 0..n.  Called by every thread of the workgroup.
+__device__ __forceinline__ WinBuckets build_buckets(const double* sw, int nwin, uint16_t* tb) {
+    WinBuckets bm;
+    bm.lo = sw[0];
+    const double width = sw[nwin - 1] - bm.lo;
+    double sc = (width > 0.0) ? static_cast<double>(kBuckets) / width : 0.0;
+    if (!(sc <= 1.0e300)) sc = 0.0;
+    bm.scale = sc;
+    const int n = nwin - 1;
+    for (int i = threadIdx.x; i < n; i += kThreads) {
+        const int bp = (i == 0) ? -1 : bm.of(sw[i - 1]);
+        const int bi = bm.of(sw[i]);
+        for (int b = bp + 1; b <= bi; ++b) tb[b] = static_cast<uint16_t>(i);
+    }
+    const int blast = (n == 0) ? -1 : bm.of(sw[n - 1]);
+    for (int b = blast + 1 + static_cast<int>(threadIdx.x); b <= kBuckets; b += kThreads)
+        tb[b] = static_cast<uint16_t>(n);
+    return bm;
+}
+
 // Places this thread's sorted values x[next..nmine) that end in a window of
 // nwin non-decreasing values sw (those not above the window's last value, or
 // all that remain in the final window): each one's position is the count of
-// window entries below it among the first nwin-1, found by bisection for the
-// first and by galloping forward from the previous one for the others.
-// res[q] = base + position; next moves past the values placed.
-__device__ __forceinline__ void place_in_window(const double* sw, int nwin, bool final_window,
+// window entries below it among the first nwin-1.  For a value v in bucket b
+// that count lies in [tb[b], tb[b+1]] (the monotone bucket map), and a
+// bisection of that range finds it; the ranges of kPlaceGroup values are
+// bisected together, so their LDS reads are in flight at once.
+// res[q] = base + position; next moves past the values placed.  Called by
+// every thread of the workgroup (the table is built here); tb holds
+// kBuckets + 1 entries of LDS.
+__device__ __forceinline__ void place_in_window(const double* sw, uint16_t* tb, int nwin,
+                                                bool final_window,
                                                 const double (&x)[kDensePer], int nmine,
                                                 int64_t base, int& next,
                                                 int32_t (&res)[kDensePer]) {
+    const WinBuckets bm = build_buckets(sw, nwin, tb);
+    lds_barrier();
     const double wend = sw[nwin - 1];
-    int pos = -1;
+    int nxt = next;
 #pragma unroll
-    for (int q = 0; q < kDensePer; ++q) {
-        if (q >= next && q < nmine && (final_window || x[q] <= wend)) {
-            const double v = x[q];
-            if (pos < 0) {
-                // count of entries below v among the first nwin-1
-                int cnt = 0;
+    for (int g = 0; g < kDensePer; g += kPlaceGroup) {
+        if (g < nmine) {
+            int a[kPlaceGroup], e[kPlaceGroup];   // the position lies in [a, e]
 #pragma unroll
-                for (int step = kWinLen / 2; step >= 1; step >>= 1)
-                    if (cnt + step <= nwin - 1 && sw[cnt + step - 1] < v) cnt += step;
-                pos = cnt;
-            } else if (sw[pos] < v) {
-                // first j > pos with sw[j] >= v: gallop, then bisect
-                int lo = pos, step = 1;   // sw[lo] < v
-                while (lo + step < nwin - 1 && sw[lo + step] < v) {
-                    lo += step;
-                    step <<= 1;
-                }
-                int hi = (lo + step < nwin - 1) ? lo + step : nwin - 1;   // sw[hi] >= v
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (sw[mid] < v)
-                        lo = mid;
-                    else
-                        hi = mid;
-                }
-                pos = hi;
+            for (int k = 0; k < kPlaceGroup; ++k) {
+                const int q = g + k;
+                const bool act = q >= next && q < nmine && (final_window || x[q] <= wend);
+                const int b = bm.of(x[q]);
+                const int ta = tb[b];
+                const int te = tb[b + 1];
+                a[k] = act ? ta : 0;
+                e[k] = act ? te : 0;
+                if (act) nxt = q + 1;
             }
-            res[q] = static_cast<int32_t>(base + pos);
-            next = q + 1;
+            // a and e stay in 0..nwin-1, so every probe reads inside the window
+            for (;;) {
+                int m[kPlaceGroup];
+                double sv[kPlaceGroup];
+#pragma unroll
+                for (int k = 0; k < kPlaceGroup; ++k) m[k] = (a[k] + e[k]) >> 1;
+#pragma unroll
+                for (int k = 0; k < kPlaceGroup; ++k) sv[k] = sw[m[k]];
+                bool more = false;
+#pragma unroll
+                for (int k = 0; k < kPlaceGroup; ++k) {
+                    const bool go = a[k] < e[k];
+                    const bool below = sv[k] < x[g + k];
+                    a[k] = (go && below) ? m[k] + 1 : a[k];
+                    e[k] = (go && !below) ? m[k] : e[k];
+                    more = more || a[k] < e[k];
+                }
+                if (!more) break;
+            }
+#pragma unroll
+            for (int k = 0; k < kPlaceGroup; ++k) {
+                const int q = g + k;
+                if (q >= next && q < nxt) res[q] = static_cast<int32_t>(base + a[k]);
+            }
         }
     }
+    next = nxt;
 }
 
-template <typename Src>
-__device__ __forceinline__ void k_map_dense_body(Src w, WArgs wa, ZArgs za, SharedArgs sh, double* __restrict__ u_out, int32_t* __restrict__ r, int32_t* __restrict__ wide, int per_wg) {
-    using Elem = typename SrcElem<Src>::type;
-    // block ends for the search of the span, then a window of normalised
-    // cumulative weights
-    __shared__ double lds[kBetaLds];
-    double* const sbeta = lds;
-    double* const sw = lds;
-    __shared__ double ltot[kThreads];
-    __shared__ int64_t span_ends[2];
+// Spans of the dense-map chunks: chunk c (uniforms c*per_wg .. c1-1) covers
+// the sub-tiles from that of its first uniform to that of its last (the split
+// of Alg. 5).  One quad locates each end, 32 chunks per workgroup;
+// span[2c] and span[2c+1] receive the global sub-tile ids.  Nothing is
+// written when the status is not ok (the map then writes -1 without reading
+// the spans).
+__global__ __launch_bounds__(kThreads) void k_dense_span(WArgs wa, ZArgs za, SharedArgs sh,
+                                                         int64_t* __restrict__ span, int per_wg,
+                                                         int64_t nchunks) {
+    __shared__ double sbeta[kBetaLds];
     const int t = threadIdx.x;
-    const int64_t N = za.N;
     const int64_t nb = wa.nb;
     const int64_t kstride = (nb + kBetaLds - 1) / kBetaLds;
     const int ns = static_cast<int>((nb + kstride - 1) / kstride);
@@ -1235,18 +1295,87 @@ __device__ __forceinline__ void k_map_dense_body(Src w, WArgs wa, ZArgs za, Shar
         const int64_t b = (static_cast<int64_t>(q) + 1) * kstride - 1;
         sbeta[q] = wa.beta[b < nb ? b : nb - 1];
     }
+    const bool ok = sh.status[0] == kStatusOk;
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * (kThreads / kQuad) + t / kQuad;
+    const int64_t c = e >> 1;
+    const bool mine = ok && c < nchunks;   // the same for the four lanes of a quad
+    double x = 0.0;
+    if (mine) {
+        const int64_t c0 = c * per_wg;
+        const int64_t c1 = (c0 + per_wg < za.N) ? c0 + per_wg : za.N;
+        x = threshold_for(uniform_at(za, sh.totals[1], (e & 1) ? c1 - 1 : c0), sh.totals[0]);
+    }
+    lds_barrier();   // the block ends are in LDS
+    if (!mine) return;
+    const int64_t g = locate_subtile_index(wa, sbeta, kstride, ns, x, t & (kQuad - 1));
+    if ((t & (kQuad - 1)) == 0) span[e] = g;
+}
+
+// The loads one thread makes for a window row: its lane chunk of global
+// sub-tile ws0 + row and the bases that chunk's cumulative values need.
+template <typename Elem>
+struct WinRowLoad {
+    RawChunk<Elem> rc;
+    double sigma, X, beta_b, beta_n;
+    int nv;
+};
+
+template <typename Src>
+__device__ __forceinline__ WinRowLoad<typename SrcElem<Src>::type> window_row_load(
+    Src w, const WArgs& wa, int64_t ws0, int64_t gs1, int row, int lane) {
+    WinRowLoad<typename SrcElem<Src>::type> L;
+    const int nw = static_cast<int>((gs1 - ws0 + 1 < kWinSub) ? gs1 - ws0 + 1 : kWinSub);
+    const int64_t gs = ws0 + row;
+    const int64_t b = gs / kWSubPerBlock;
+    const int sb = static_cast<int>(gs % kWSubPerBlock);
+    const int64_t j0 = b * kWBlock + static_cast<int64_t>(sb) * kSub + lane * kLane;
+    L.nv = (row < nw) ? clamp_count(wa.M - j0, kLane) : 0;
+    L.sigma = 0.0;
+    L.X = 0.0;
+    L.beta_b = 0.0;
+    L.beta_n = 0.0;
+    if (L.nv > 0) {
+        L.sigma = (sb == 0) ? 0.0 : wa.sub_end[b * kWSubPerBlock + sb - 1];
+        L.X = wa.sub_end[b * kWSubPerBlock + kWSubPerBlock - 1];
+        L.beta_b = (b == 0) ? 0.0 : wa.beta[b - 1];
+        L.beta_n = wa.beta[b];
+    }
+    L.rc = src_raw_n(w, j0, L.nv);
+    return L;
+}
+
+template <typename Src>
+__device__ __forceinline__ void k_map_dense_body(Src w, WArgs wa, ZArgs za, SharedArgs sh, const int64_t* __restrict__ span, double* __restrict__ u_out, int32_t* __restrict__ r, int32_t* __restrict__ wide, int per_wg) {
+    using Elem = typename SrcElem<Src>::type;
+    // a window of normalised cumulative weights, its bucket table and the
+    // lane-chunk totals of its rows
+    __shared__ double sw[kWinLen];
+    __shared__ double ltot[kThreads];
+    __shared__ uint16_t tb[kBuckets + 1];
+    const int t = threadIdx.x;
+    const int64_t N = za.N;
     const int64_t c0 = static_cast<int64_t>(blockIdx.x) * per_wg;
     const int64_t c1 = (c0 + per_wg < N) ? c0 + per_wg : N;
-    const int nu = static_cast<int>(c1 - c0);
     const bool ok = sh.status[0] == kStatusOk;
     const double total = sh.totals[0];
     const double ztot = sh.totals[1];
     const int64_t iu0 = c0 + static_cast<int64_t>(t) * kDensePer;
     const int nmine = clamp_count(c1 - iu0, kDensePer);
-    // the first and the last uniform of the chunk, for the span search by
-    // quads 0 and 1: formed first, so that the search overlaps the rest
-    double uend = 0.0;
-    if (t < 2 * kQuad && nu > 0) uend = uniform_at(za, ztot, (t < kQuad) ? c0 : c1 - 1);
+    if (!ok) {
+        for (int q = 0; q < nmine; ++q) r[iu0 + q] = -1;
+        if (t == 0) wide[blockIdx.x] = 0;
+        return;
+    }
+    // the chunk's span of sub-tiles; a span wider than kMaxWin windows is
+    // left to k_map_wide
+    const int64_t gs0 = span[2 * static_cast<int64_t>(blockIdx.x)];
+    const int64_t gs1 = span[2 * static_cast<int64_t>(blockIdx.x) + 1];
+    const bool is_wide = gs1 - gs0 + 1 > static_cast<int64_t>(kWinSub) * kMaxWin;
+    const int row = t / kRowLanes;
+    const int lane = t % kRowLanes;
+    // the first window's loads go out before the uniforms are formed
+    WinRowLoad<Elem> cur{};
+    if (!is_wide) cur = window_row_load(w, wa, gs0, gs1, row, lane);
     // this thread's 16 draws lie in one spacing block (16 divides 4096 and
     // per_wg): load their in-block prefixes at once, then form the uniforms
     double us[kDensePer];
@@ -1273,53 +1402,21 @@ __device__ __forceinline__ void k_map_dense_body(Src w, WArgs wa, ZArgs za, Shar
 #pragma unroll
         for (int q = 0; q < kDensePer; ++q) us[q] = uniform_of(us[q], iu0 + q, N, zb, zn, ztot);
     }
-    lds_barrier();   // the block ends are in LDS
-    if (!ok) {
-        for (int q = 0; q < nmine; ++q) r[iu0 + q] = -1;
-        if (t == 0) wide[blockIdx.x] = 0;
-        return;
-    }
-    // global sub-tile ids of the first and the last uniform (quads 0 and 1)
-    if (t < 2 * kQuad) {
-        const double xe = threshold_for(uend, total);
-        const int64_t g = locate_subtile_index(wa, sbeta, kstride, ns, xe, t & (kQuad - 1));
-        if ((t & (kQuad - 1)) == 0) span_ends[t / kQuad] = g;
-    }
     if (u_out) store_uniforms(u_out, iu0, nmine, us, (reinterpret_cast<uintptr_t>(u_out) & 15) == 0);
-    lds_barrier();
-    const int64_t gs0 = span_ends[0], gs1 = span_ends[1];
-    const bool is_wide = gs1 - gs0 + 1 > static_cast<int64_t>(kWinSub) * kMaxWin;
     if (t == 0) wide[blockIdx.x] = is_wide ? 1 : 0;
     if (is_wide) return;
-    const int row = t / kRowLanes;
-    const int lane = t % kRowLanes;
     int32_t res[kDensePer];
     int next = 0;   // this thread's first draw not placed yet (the draws are sorted)
 #pragma unroll
     for (int q = 0; q < kDensePer; ++q) res[q] = 0;
-    for (int64_t ws0 = gs0; ws0 <= gs1; ws0 += kWinSub) {
+    // one window: row r holds global sub-tile ws0 + r, so thread t writes
+    // window entries 16t .. 16t+15, then the draws that end in it are placed
+    auto window = [&](const WinRowLoad<Elem>& L, int64_t ws0) {
         const int nw = static_cast<int>((gs1 - ws0 + 1 < kWinSub) ? gs1 - ws0 + 1 : kWinSub);
-        // re-sum the window: row r takes global sub-tile ws0 + r, so thread t
-        // writes window entries 16t .. 16t+15
-        const int64_t gs = ws0 + row;
-        const int64_t b = gs / kWSubPerBlock;
-        const int sb = static_cast<int>(gs % kWSubPerBlock);
-        const int64_t blk0 = b * kWBlock;
-        const int64_t j0 = blk0 + static_cast<int64_t>(sb) * kSub + lane * kLane;
-        const int nv = (row < nw) ? clamp_count(wa.M - j0, kLane) : 0;
-        // every load of the window first: its weights and the bases they need
-        double sigma = 0.0, beta_b = 0.0, beta_n = 0.0, X = 0.0;
-        if (nv > 0) {
-            sigma = (sb == 0) ? 0.0 : wa.sub_end[b * kWSubPerBlock + sb - 1];
-            X = wa.sub_end[b * kWSubPerBlock + kWSubPerBlock - 1];
-            beta_b = (b == 0) ? 0.0 : wa.beta[b - 1];
-            beta_n = wa.beta[b];
-        }
-        const RawChunk<Elem> rc = src_raw_n(w, j0, nv);
         {
-            double pt = rc.at(0);
+            double pt = L.rc.at(0);
 #pragma unroll
-            for (int k = 1; k < kLane; ++k) pt = pt + rc.at(k);
+            for (int k = 1; k < kLane; ++k) pt = pt + L.rc.at(k);
             ltot[t] = pt;
         }
         lds_barrier();
@@ -1330,17 +1427,20 @@ __device__ __forceinline__ void k_map_dense_body(Src w, WArgs wa, ZArgs za, Shar
         double pk = 0.0;
 #pragma unroll
         for (int k = 0; k < kLane; ++k) {
-            pk = (k == 0) ? rc.at(0) : pk + rc.at(k);
-            const double S = block_end_at(sigma + (c + pk), X, beta_b, beta_n);
-            sw[t * kLane + k] = (k < nv) ? S / total : __builtin_huge_val();
+            pk = (k == 0) ? L.rc.at(0) : pk + L.rc.at(k);
+            const double S = block_end_at(L.sigma + (c + pk), L.X, L.beta_b, L.beta_n);
+            sw[t * kLane + k] = (k < L.nv) ? S / total : __builtin_huge_val();
         }
         lds_barrier();
         // entries of the window that exist
         const int64_t wlen64 = wa.M - ws0 * kSub;
         const int nwin = (nw * kSub < wlen64) ? nw * kSub : static_cast<int>(wlen64);
-        place_in_window(sw, nwin, false, us, nmine, ws0 * kSub, next, res);
-        lds_barrier();   // ltot and the window are rewritten by the next window
-    }
+        place_in_window(sw, tb, nwin, false, us, nmine, ws0 * kSub, next, res);
+        lds_barrier();   // ltot, the window and its table are rewritten by the next window
+    };
+    window(cur, gs0);   // the loads made before the uniforms
+    for (int64_t ws0 = gs0 + kWinSub; ws0 <= gs1; ws0 += kWinSub)
+        window(window_row_load(w, wa, ws0, gs1, row, lane), ws0);
     if (nmine == kDensePer && (reinterpret_cast<uintptr_t>(r + iu0) & 15) == 0) {
         int4* dst = reinterpret_cast<int4*>(r + iu0);
 #pragma unroll
@@ -1354,13 +1454,13 @@ __device__ __forceinline__ void k_map_dense_body(Src w, WArgs wa, ZArgs za, Shar
 }
 
 template <typename Tin>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_map_dense(const Tin* __restrict__ w, WArgs wa, ZArgs za, SharedArgs sh, double* __restrict__ u_out, int32_t* __restrict__ r, int32_t* __restrict__ wide, int per_wg) {
-    k_map_dense_body<const Tin*>(w, wa, za, sh, u_out, r, wide, per_wg);
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_map_dense(const Tin* __restrict__ w, WArgs wa, ZArgs za, SharedArgs sh, const int64_t* __restrict__ span, double* __restrict__ u_out, int32_t* __restrict__ r, int32_t* __restrict__ wide, int per_wg) {
+    k_map_dense_body<const Tin*>(w, wa, za, sh, span, u_out, r, wide, per_wg);
 }
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_map_dense_outer(Outer<T> w, WArgs wa, ZArgs za, SharedArgs sh, double* __restrict__ u_out, int32_t* __restrict__ r, int32_t* __restrict__ wide, int per_wg) {
-    k_map_dense_body<Outer<T>>(w, wa, za, sh, u_out, r, wide, per_wg);
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_map_dense_outer(Outer<T> w, WArgs wa, ZArgs za, SharedArgs sh, const int64_t* __restrict__ span, double* __restrict__ u_out, int32_t* __restrict__ r, int32_t* __restrict__ wide, int per_wg) {
+    k_map_dense_body<Outer<T>>(w, wa, za, sh, span, u_out, r, wide, per_wg);
 }
 
 // The flagged (wide-span) chunks of k_map_dense: one quad search per uniform.
@@ -1743,6 +1843,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     const double* __restrict__ W, int64_t M, const double* __restrict__ u, int64_t N,
     int32_t* __restrict__ r, int per_wg) {
     __shared__ double sw[kWinLen];
+    __shared__ uint16_t tb[kBuckets + 1];
     __shared__ int64_t range[2];
     const int t = threadIdx.x;
     const int64_t c0 = static_cast<int64_t>(blockIdx.x) * per_wg;
@@ -1766,7 +1867,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
         const int nwin = static_cast<int>((hi + 1 - ws0 < kWinLen) ? hi + 1 - ws0 : kWinLen);
         for (int k = t; k < nwin; k += kThreads) sw[k] = W[ws0 + k];
         lds_barrier();
-        place_in_window(sw, nwin, ws0 + kWinLen > hi, x, nmine, ws0, next, res);
+        place_in_window(sw, tb, nwin, ws0 + kWinLen > hi, x, nmine, ws0, next, res);
         lds_barrier();   // the window is rewritten next
     }
     if (nmine == kDensePer && (reinterpret_cast<uintptr_t>(r + iu0) & 15) == 0) {
@@ -2587,9 +2688,21 @@ int64_t dense_chunks(int64_t M, int64_t N) {
     return (N + per - 1) / per;
 }
 
+hipError_t launch_dense_span(const WArgs& wa, const ZArgs& za, const SharedArgs& sh, int64_t* span,
+                             hipStream_t s) {
+    if (za.N <= 0) return hipSuccess;
+    const int per = dense_per_wg(wa.M, za.N);
+    const int64_t chunks = dense_chunks(wa.M, za.N);
+    constexpr int64_t kEndsPerWG = kThreads / kQuad;
+    const int64_t grid = (2 * chunks + kEndsPerWG - 1) / kEndsPerWG;
+    launch(k_dense_span, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s, wa, za, sh, span,
+           per, chunks);
+    return take_launch_status();
+}
+
 hipError_t launch_map_dense(int prec, const WSource& src, const WArgs& wa, const ZArgs& za,
-                            const SharedArgs& sh, double* u_out, int32_t* r, int32_t* wide,
-                            hipStream_t s) {
+                            const SharedArgs& sh, const int64_t* span, double* u_out, int32_t* r,
+                            int32_t* wide, hipStream_t s) {
     if (za.N <= 0) return hipSuccess;
     const int per = dense_per_wg(wa.M, za.N);
     const int64_t grid = dense_chunks(wa.M, za.N);
@@ -2597,16 +2710,16 @@ hipError_t launch_map_dense(int prec, const WSource& src, const WArgs& wa, const
     if (src.outer()) {
         if (prec == kPrecFP32)
             launch(k_map_dense_outer<float>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s,
-                   src.outer_as<float>(), wa, za, sh, u_out, r, wide, per);
+                   src.outer_as<float>(), wa, za, sh, span, u_out, r, wide, per);
         else
             launch(k_map_dense_outer<double>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0,
-                   s, src.outer_as<double>(), wa, za, sh, u_out, r, wide, per);
+                   s, src.outer_as<double>(), wa, za, sh, span, u_out, r, wide, per);
     } else if (prec == kPrecFP32)
         launch(k_map_dense<float>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s,
-               static_cast<const float*>(w), wa, za, sh, u_out, r, wide, per);
+               static_cast<const float*>(w), wa, za, sh, span, u_out, r, wide, per);
     else
         launch(k_map_dense<double>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s,
-               static_cast<const double*>(w), wa, za, sh, u_out, r, wide, per);
+               static_cast<const double*>(w), wa, za, sh, span, u_out, r, wide, per);
     return take_launch_status();
 }
 
