@@ -86,7 +86,7 @@ def load_traffic(workload: str, precision: str, kernel: str):
 
 # kernel of each timed launch kind
 KERNEL_NAMES = {"reduce": "k_reduce", "finish": "k_finish", "map_dense": "k_map_dense",
-                "map_fused": "k_map_fused", "carries": "k_carries", "map_wide": "k_map_wide",
+                "map_fused": "k_map_fused", "carries": "k_carries",
                 "batch_reduce": "k_reduce_batched", "batch_map": "k_map_batched",
                 "batch_carries": "k_carries_batched", "map_span": "k_dense_span"}
 KIND_OF_KERNEL = {v: k for k, v in KERNEL_NAMES.items()}

@@ -39,11 +39,11 @@ struct Layout {
     size_t status = 0, totals = 0;
     size_t w_tot = 0, w_beta = 0, w_sub = 0;
     size_t z_tot = 0, z_beta = 0, z_buf = 0;
-    size_t wide = 0, span = 0;
+    size_t span = 0;
     size_t bytes = 0;
 };
 
-// Workspace layout: [header][weight side][spacing side][dense-map flags and spans];
+// Workspace layout: [header][weight side][spacing side][dense-map chunk spans];
 // the stratified and systematic schemes have no spacing side.
 Layout make_layout(int64_t M, int64_t N, int scheme = dcr::kSchemeMultinomial) {
     Layout L;
@@ -72,8 +72,6 @@ Layout make_layout(int64_t M, int64_t N, int scheme = dcr::kSchemeMultinomial) {
     }
     if (N > 0) {
         const size_t chunks = (N + kDenseMinPerWG - 1) / kDenseMinPerWG;
-        L.wide = off;
-        off = align256(off + sizeof(int32_t) * chunks);
         L.span = off;
         off = align256(off + 2 * sizeof(int64_t) * chunks);
     }
@@ -125,13 +123,13 @@ SharedArgs shared_args(const Layout& L, void* ws) {
 // Optional kernel timing (dcr_profile_*).
 // ---------------------------------------------------------------------------
 enum Kind {
-    kKReduce = 0, kKCarries, kKMatW, kKMatU, kKMapFused, kKMapW, kKFinish, kKMapDense, kKMapWide,
-    kKBatchPlan, kKBatchReduce, kKBatchCarries, kKBatchMap, kKMapSpan, kNumKinds
+    kKReduce = 0, kKCarries, kKMatW, kKMatU, kKMapFused, kKMapW, kKFinish, kKMapDense, kKMapSpan,
+    kKBatchPlan, kKBatchReduce, kKBatchCarries, kKBatchMap, kNumKinds
 };
 const char* const kKindNames[kNumKinds] = {"reduce",   "carries", "materialize_w", "materialize_u",
                                            "map_fused", "map_w",  "finish",        "map_dense",
-                                           "map_wide",  "batch_plan", "batch_reduce",
-                                           "batch_carries", "batch_map", "map_span"};
+                                           "map_span",  "batch_plan", "batch_reduce",
+                                           "batch_carries", "batch_map"};
 
 struct Profiler {
     bool on = false;
@@ -462,7 +460,6 @@ dcr_status resample_from(const dcr::WSource& src, int64_t M, int64_t N, uint64_t
     const int prec = prec_code(p);
     // an outer product has no alignment to honour
     const int vec = ((src.outer() || aligned16(src.w)) ? 1 : 0) | (aligned16(W_opt) ? 2 : 0);
-    int32_t* wide = at<int32_t>(ws, L.wide);
     int64_t* span = at<int64_t>(ws, L.span);
     // a few weight blocks: 1024 threads per block, the same sums
     hipError_t e = timed(kKReduce, stream, [&] {
@@ -492,11 +489,7 @@ dcr_status resample_from(const dcr::WSource& src, int64_t M, int64_t N, uint64_t
                       [&] { return dcr::launch_dense_span(wa, za, sh, span, stream); });
             if (e == hipSuccess)
                 e = timed(kKMapDense, stream, [&] {
-                    return dcr::launch_map_dense(prec, src, wa, za, sh, span, u_opt, r, wide, stream);
-                });
-            if (e == hipSuccess)
-                e = timed(kKMapWide, stream, [&] {
-                    return dcr::launch_map_wide(prec, src, wa, za, sh, r, wide, vec, stream);
+                    return dcr::launch_map_dense(prec, src, wa, za, sh, span, u_opt, r, vec, stream);
                 });
         } else
             e = timed(kKMapFused, stream, [&] {

@@ -15,7 +15,7 @@
 //                       256-weight sub-tile), the divide-and-conquer map of
 //                       Alg. 5 laid onto the block / sub-tile / element levels
 //   k_map_dense         inverse CMF when N >= M/4: the linear merge of Alg. 4
-//   k_map_wide          the chunks k_map_dense leaves (spans too wide to merge)
+//   k_dense_span        the span of sub-tiles of every chunk of the dense map
 //   k_map_w, k_map_w_dense
 //                       inverse CMF against a given W (stage 3 alone)
 // Every kernel that reads weights has an `_outer` twin for weights given as
@@ -1160,9 +1160,8 @@ __global__ __launch_bounds__(kThreads) void k_map_fused_outer(Outer<T> w, WArgs 
 // end in the window (the merge of Alg. 4, one run of uniforms per thread):
 // a table of the window's value buckets narrows each uniform's search to a
 // few entries, and the short bisections of several uniforms run
-// interleaved, so no thread waits on a long chain of LDS reads.  A span wider
-// than 64 sub-tiles is flagged and left to k_map_wide (one quad search per
-// uniform).
+// interleaved, so no thread waits on a long chain of LDS reads.  A chunk whose
+// span is wider than 64 sub-tiles takes one quad search per uniform instead.
 // ---------------------------------------------------------------------------
 constexpr int kDenseU = 4096;                 // most uniforms per workgroup
 constexpr int kDensePer = kDenseU / kThreads;  // per thread
@@ -1344,8 +1343,30 @@ __device__ __forceinline__ WinRowLoad<typename SrcElem<Src>::type> window_row_lo
     return L;
 }
 
+// A chunk whose span is too wide for the windows: one quad search per
+// uniform, with the block ends staged in sbeta (kBetaLds doubles of LDS).
+// Called by every thread of the workgroup.
 template <typename Src>
-__device__ __forceinline__ void k_map_dense_body(Src w, WArgs wa, ZArgs za, SharedArgs sh, const int64_t* __restrict__ span, double* __restrict__ u_out, int32_t* __restrict__ r, int32_t* __restrict__ wide, int per_wg) {
+__device__ __forceinline__ void map_wide_chunk(Src w, const WArgs& wa, const ZArgs& za, double total,
+                                               double ztot, int64_t c0, int64_t c1,
+                                               int32_t* __restrict__ r, int vec_ok, double* sbeta) {
+    const int t = threadIdx.x;
+    const int64_t nb = wa.nb;
+    const int64_t kstride = (nb + kBetaLds - 1) / kBetaLds;
+    const int ns = static_cast<int>((nb + kstride - 1) / kstride);
+    for (int q = t; q < ns; q += kThreads) {
+        const int64_t b = (static_cast<int64_t>(q) + 1) * kstride - 1;
+        sbeta[q] = wa.beta[b < nb ? b : nb - 1];
+    }
+    lds_barrier();
+    for (int64_t i = c0 + t / kQuad; i < c1; i += kUPerWG) {
+        const double x = threshold_for(uniform_at(za, ztot, i), total);
+        map_quad<Src>(w, wa, sbeta, kstride, ns, x, i, t & (kQuad - 1), r, vec_ok);
+    }
+}
+
+template <typename Src>
+__device__ __forceinline__ void k_map_dense_body(Src w, WArgs wa, ZArgs za, SharedArgs sh, const int64_t* __restrict__ span, double* __restrict__ u_out, int32_t* __restrict__ r, int vec_ok, int per_wg) {
     using Elem = typename SrcElem<Src>::type;
     // a window of normalised cumulative weights, its bucket table and the
     // lane-chunk totals of its rows
@@ -1363,11 +1384,10 @@ __device__ __forceinline__ void k_map_dense_body(Src w, WArgs wa, ZArgs za, Shar
     const int nmine = clamp_count(c1 - iu0, kDensePer);
     if (!ok) {
         for (int q = 0; q < nmine; ++q) r[iu0 + q] = -1;
-        if (t == 0) wide[blockIdx.x] = 0;
         return;
     }
-    // the chunk's span of sub-tiles; a span wider than kMaxWin windows is
-    // left to k_map_wide
+    // the chunk's span of sub-tiles; a span wider than kMaxWin windows takes
+    // one quad search per uniform instead (map_wide_chunk)
     const int64_t gs0 = span[2 * static_cast<int64_t>(blockIdx.x)];
     const int64_t gs1 = span[2 * static_cast<int64_t>(blockIdx.x) + 1];
     const bool is_wide = gs1 - gs0 + 1 > static_cast<int64_t>(kWinSub) * kMaxWin;
@@ -1403,8 +1423,10 @@ __device__ __forceinline__ void k_map_dense_body(Src w, WArgs wa, ZArgs za, Shar
         for (int q = 0; q < kDensePer; ++q) us[q] = uniform_of(us[q], iu0 + q, N, zb, zn, ztot);
     }
     if (u_out) store_uniforms(u_out, iu0, nmine, us, (reinterpret_cast<uintptr_t>(u_out) & 15) == 0);
-    if (t == 0) wide[blockIdx.x] = is_wide ? 1 : 0;
-    if (is_wide) return;
+    if (is_wide) {   // workgroup-uniform
+        map_wide_chunk<Src>(w, wa, za, total, ztot, c0, c1, r, vec_ok, sw);
+        return;
+    }
     int32_t res[kDensePer];
     int next = 0;   // this thread's first draw not placed yet (the draws are sorted)
 #pragma unroll
@@ -1454,47 +1476,13 @@ __device__ __forceinline__ void k_map_dense_body(Src w, WArgs wa, ZArgs za, Shar
 }
 
 template <typename Tin>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_map_dense(const Tin* __restrict__ w, WArgs wa, ZArgs za, SharedArgs sh, const int64_t* __restrict__ span, double* __restrict__ u_out, int32_t* __restrict__ r, int32_t* __restrict__ wide, int per_wg) {
-    k_map_dense_body<const Tin*>(w, wa, za, sh, span, u_out, r, wide, per_wg);
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_map_dense(const Tin* __restrict__ w, WArgs wa, ZArgs za, SharedArgs sh, const int64_t* __restrict__ span, double* __restrict__ u_out, int32_t* __restrict__ r, int vec_ok, int per_wg) {
+    k_map_dense_body<const Tin*>(w, wa, za, sh, span, u_out, r, vec_ok, per_wg);
 }
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_map_dense_outer(Outer<T> w, WArgs wa, ZArgs za, SharedArgs sh, const int64_t* __restrict__ span, double* __restrict__ u_out, int32_t* __restrict__ r, int32_t* __restrict__ wide, int per_wg) {
-    k_map_dense_body<Outer<T>>(w, wa, za, sh, span, u_out, r, wide, per_wg);
-}
-
-// The flagged (wide-span) chunks of k_map_dense: one quad search per uniform.
-template <typename Src>
-__device__ __forceinline__ void k_map_wide_body(Src w, WArgs wa, ZArgs za, SharedArgs sh, int32_t* __restrict__ r, const int32_t* __restrict__ wide, int vec_ok, int per_wg) {
-    __shared__ double sbeta[kBetaLds];
-    if (wide[blockIdx.x] == 0) return;   // workgroup-uniform
-    const int t = threadIdx.x;
-    const int64_t nb = wa.nb;
-    const int64_t kstride = (nb + kBetaLds - 1) / kBetaLds;
-    const int ns = static_cast<int>((nb + kstride - 1) / kstride);
-    for (int q = t; q < ns; q += kThreads) {
-        const int64_t b = (static_cast<int64_t>(q) + 1) * kstride - 1;
-        sbeta[q] = wa.beta[b < nb ? b : nb - 1];
-    }
-    lds_barrier();
-    const double total = sh.totals[0];
-    const double ztot = sh.totals[1];
-    const int64_t c0 = static_cast<int64_t>(blockIdx.x) * per_wg;
-    const int64_t c1 = (c0 + per_wg < za.N) ? c0 + per_wg : za.N;
-    for (int64_t i = c0 + t / kQuad; i < c1; i += kUPerWG) {
-        const double x = threshold_for(uniform_at(za, ztot, i), total);
-        map_quad<Src>(w, wa, sbeta, kstride, ns, x, i, t & (kQuad - 1), r, vec_ok);
-    }
-}
-
-template <typename Tin>
-__global__ __launch_bounds__(kThreads) void k_map_wide(const Tin* __restrict__ w, WArgs wa, ZArgs za, SharedArgs sh, int32_t* __restrict__ r, const int32_t* __restrict__ wide, int vec_ok, int per_wg) {
-    k_map_wide_body<const Tin*>(w, wa, za, sh, r, wide, vec_ok, per_wg);
-}
-
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_map_wide_outer(Outer<T> w, WArgs wa, ZArgs za, SharedArgs sh, int32_t* __restrict__ r, const int32_t* __restrict__ wide, int vec_ok, int per_wg) {
-    k_map_wide_body<Outer<T>>(w, wa, za, sh, r, wide, vec_ok, per_wg);
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_map_dense_outer(Outer<T> w, WArgs wa, ZArgs za, SharedArgs sh, const int64_t* __restrict__ span, double* __restrict__ u_out, int32_t* __restrict__ r, int vec_ok, int per_wg) {
+    k_map_dense_body<Outer<T>>(w, wa, za, sh, span, u_out, r, vec_ok, per_wg);
 }
 
 // ---------------------------------------------------------------------------
@@ -2702,7 +2690,7 @@ hipError_t launch_dense_span(const WArgs& wa, const ZArgs& za, const SharedArgs&
 
 hipError_t launch_map_dense(int prec, const WSource& src, const WArgs& wa, const ZArgs& za,
                             const SharedArgs& sh, const int64_t* span, double* u_out, int32_t* r,
-                            int32_t* wide, hipStream_t s) {
+                            int vec_ok, hipStream_t s) {
     if (za.N <= 0) return hipSuccess;
     const int per = dense_per_wg(wa.M, za.N);
     const int64_t grid = dense_chunks(wa.M, za.N);
@@ -2710,39 +2698,16 @@ hipError_t launch_map_dense(int prec, const WSource& src, const WArgs& wa, const
     if (src.outer()) {
         if (prec == kPrecFP32)
             launch(k_map_dense_outer<float>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s,
-                   src.outer_as<float>(), wa, za, sh, span, u_out, r, wide, per);
+                   src.outer_as<float>(), wa, za, sh, span, u_out, r, vec_ok, per);
         else
             launch(k_map_dense_outer<double>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0,
-                   s, src.outer_as<double>(), wa, za, sh, span, u_out, r, wide, per);
+                   s, src.outer_as<double>(), wa, za, sh, span, u_out, r, vec_ok, per);
     } else if (prec == kPrecFP32)
         launch(k_map_dense<float>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s,
-               static_cast<const float*>(w), wa, za, sh, span, u_out, r, wide, per);
+               static_cast<const float*>(w), wa, za, sh, span, u_out, r, vec_ok, per);
     else
         launch(k_map_dense<double>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s,
-               static_cast<const double*>(w), wa, za, sh, span, u_out, r, wide, per);
-    return take_launch_status();
-}
-
-hipError_t launch_map_wide(int prec, const WSource& src, const WArgs& wa, const ZArgs& za,
-                           const SharedArgs& sh, int32_t* r, const int32_t* wide, int vec_ok,
-                           hipStream_t s) {
-    if (za.N <= 0) return hipSuccess;
-    const int per = dense_per_wg(wa.M, za.N);
-    const int64_t grid = dense_chunks(wa.M, za.N);
-    const void* w = src.w;
-    if (src.outer()) {
-        if (prec == kPrecFP32)
-            launch(k_map_wide_outer<float>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s,
-                   src.outer_as<float>(), wa, za, sh, r, wide, 1, per);
-        else
-            launch(k_map_wide_outer<double>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s,
-                   src.outer_as<double>(), wa, za, sh, r, wide, 1, per);
-    } else if (prec == kPrecFP32)
-        launch(k_map_wide<float>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s,
-               static_cast<const float*>(w), wa, za, sh, r, wide, vec_ok, per);
-    else
-        launch(k_map_wide<double>, dim3(static_cast<unsigned>(grid)), dim3(kThreads), 0, s,
-               static_cast<const double*>(w), wa, za, sh, r, wide, vec_ok, per);
+               static_cast<const double*>(w), wa, za, sh, span, u_out, r, vec_ok, per);
     return take_launch_status();
 }
 

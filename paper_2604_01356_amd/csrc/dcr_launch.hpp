@@ -44,16 +44,11 @@ int64_t dense_chunks(int64_t M, int64_t N);   // at most ceil(N / 256)
 // dense map, 2 * dense_chunks(M, N) int64 values in `span`.
 hipError_t launch_dense_span(const WArgs& wa, const ZArgs& za, const SharedArgs& sh, int64_t* span,
                              hipStream_t s);
-// k_map_dense: merges each chunk of draws within its span and flags in `wide`
-// (dense_chunks(M, N) int32 flags) the chunks whose span is too wide to merge;
-// launch_map_wide then places the draws of the flagged chunks.
+// k_map_dense: merges each chunk of draws within its span (chunks whose span
+// is too wide to merge take one quad search per draw in the same launch).
 hipError_t launch_map_dense(int prec, const WSource& src, const WArgs& wa, const ZArgs& za,
                             const SharedArgs& sh, const int64_t* span, double* u_out, int32_t* r,
-                            int32_t* wide, hipStream_t s);
-// the flagged (wide-span) chunks left by launch_map_dense
-hipError_t launch_map_wide(int prec, const WSource& src, const WArgs& wa, const ZArgs& za,
-                           const SharedArgs& sh, int32_t* r, const int32_t* wide, int vec_ok,
-                           hipStream_t s);
+                            int vec_ok, hipStream_t s);
 
 hipError_t launch_carries(const WArgs& wa, const ZArgs& za, const SharedArgs& sh,
                           int32_t* dev_status, double* total_out, hipStream_t s);

@@ -64,6 +64,24 @@ def test_ragged_fp32(dev, dcr, M, N):
     check_against_oracle(out, w, N, 12, 0, DU_FP32, 2.0**-40)
 
 
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_dense_wide_spans(dev, dcr, dtype):
+    """Dense regime (4N >= M) with log-weights ~ N(0, 6^2): the draws pile on a
+    few heavy weights, so chunks of the dense map span far more than 64
+    sub-tiles and take the per-draw quad search; the rest merge in windows."""
+    M, N = (1 << 20) + 77, (1 << 18) + 99
+    rng = np.random.default_rng(606)
+    w = np.exp(rng.normal(0, 6, M)).astype(dtype)
+    out = run_case(dcr, dev, w, N, seed=21, stream=4, expect="map_dense")
+    r = out["r"]
+    # every dense-map chunk is a whole number of 256-draw blocks, so a block
+    # whose indices span more than 65 sub-tiles of 256 lies in a wide chunk
+    spans = r[255:N:256] - r[0:N - 255:256]
+    assert spans.max() > 65 * 256 and spans.min() < 16 * 256
+    du_cap = 1e-12 if dtype == np.float64 else DU_FP32
+    check_against_oracle(out, w, N, 21, 4, du_cap, 2.0**-40)
+
+
 @pytest.mark.parametrize("maker", ["small_single", "engmf_step"])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_paper_shaped_configs(dev, dcr, maker, dtype):
