@@ -447,6 +447,7 @@ constexpr int kScanThreads = kThreads;
 constexpr int kScanWaves = kScanThreads / 64;
 constexpr int kScanRegs = 16;   // ranges up to this length stay in registers
 constexpr int kBatchScanRegs = 4;
+constexpr int kCarryScanRegs = 32;   // k_carries: one workgroup, so registers are plentiful
 constexpr int kScanBatch = 16;  // loads in flight per thread when the ranges are longer
 
 // Per-thread inputs of a scan, loaded ahead of the computation so that the
@@ -719,7 +720,7 @@ __device__ __forceinline__ void carries_body(const WArgs& wa, const ZArgs& za, c
 __global__ __launch_bounds__(kScanThreads) void k_carries(WArgs wa, ZArgs za, SharedArgs sh,
                                                           int32_t* dev_status, double* total_out) {
     __shared__ ScanLds L;
-    carries_body(wa, za, sh, dev_status, total_out, L);
+    carries_body<kCarryScanRegs>(wa, za, sh, dev_status, total_out, L);
 }
 
 // ---------------------------------------------------------------------------
