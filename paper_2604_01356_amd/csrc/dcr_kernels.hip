@@ -148,10 +148,13 @@ __device__ __forceinline__ void reduce_w_epilogue(const double (&lt)[kWIters], i
     double* sub_end = sub_tot + kWSubPerBlock;            // [kWSubPerBlock]
     const int t = threadIdx.x;
     if (wa.chunk_tot) {
-        // lane chunk (sub-tile 16 it + row, lane) of the block: coalesced per round
+        // lane chunk (sub-tile 16 it + row, lane) of the block: coalesced per
+        // round, and non-temporal (the map reads them much later; whole lines
+        // go out together).  The lane-strided spacing prefixes are not: there
+        // every 16-byte piece would go to memory on its own
         double* ct = wa.chunk_tot + b * (kWSubPerBlock * kRowLanes);
 #pragma unroll
-        for (int it = 0; it < kWIters; ++it) ct[it * kThreads + t] = lt[it];
+        for (int it = 0; it < kWIters; ++it) __builtin_nontemporal_store(lt[it], &ct[it * kThreads + t]);
     }
     lds_barrier();   // the first stream buffer becomes the epilogue's scratch
 #pragma unroll
