@@ -1193,12 +1193,19 @@ struct WinBuckets {
     }
 };
 
-// Fills tb[0..kBuckets]: tb[b] is the first of the window's first n = nwin-1
-// entries whose bucket is >= b, or n if there is none.  Entry i writes the
-// buckets (bucket(i-1), bucket(i)]; with -1 before the first entry and
-// kBuckets after the last these runs cover every b, so each tb[b] is written
-// and holds an index in 0..n.  Called by every thread of the workgroup.
-__device__ __forceinline__ WinBuckets build_buckets(const double* sw, int nwin, uint16_t* tb) {
+// Fills tb[0..kBuckets] (16-bit entries; tbw is (kBuckets + 2) / 2 words of
+// LDS whose first kBuckets / 2 words are zero and visible to every thread when
+// this is called): tb[b] is the count of the window's first n = nwin-1
+// entries whose bucket is below b.  Along the window the buckets do not
+// decrease, so that count is the first entry whose bucket is >= b (n if none).
+// Each entry adds one to its bucket's counter (two 16-bit counters per word,
+// an entry count stays below 2^16), then the counters are scanned: thread t
+// takes buckets 8t .. 8t+7.  Every tb[b] lies in 0..n whatever the values.
+// Called by every thread of the workgroup.
+__device__ __forceinline__ WinBuckets build_buckets(const double* sw, int nwin, uint32_t* tbw) {
+    constexpr int kPerT = kBuckets / kThreads;
+    static_assert(kBuckets % kThreads == 0 && kPerT % 2 == 0, "bucket words per thread");
+    __shared__ int wtot[kThreads / 64];
     WinBuckets bm;
     bm.lo = sw[0];
     const double width = sw[nwin - 1] - bm.lo;
@@ -1206,15 +1213,47 @@ __device__ __forceinline__ WinBuckets build_buckets(const double* sw, int nwin, 
     if (!(sc <= 1.0e300)) sc = 0.0;
     bm.scale = sc;
     const int n = nwin - 1;
-    for (int i = threadIdx.x; i < n; i += kThreads) {
-        const int bp = (i == 0) ? -1 : bm.of(sw[i - 1]);
+    const int t = threadIdx.x;
+    for (int i = t; i < n; i += kThreads) {
         const int bi = bm.of(sw[i]);
-        for (int b = bp + 1; b <= bi; ++b) tb[b] = static_cast<uint16_t>(i);
+        atomicAdd(&tbw[bi >> 1], (bi & 1) ? 0x10000u : 1u);
     }
-    const int blast = (n == 0) ? -1 : bm.of(sw[n - 1]);
-    for (int b = blast + 1 + static_cast<int>(threadIdx.x); b <= kBuckets; b += kThreads)
-        tb[b] = static_cast<uint16_t>(n);
+    lds_barrier();
+    uint32_t wv[kPerT / 2];
+#pragma unroll
+    for (int j = 0; j < kPerT / 2; ++j) wv[j] = tbw[t * (kPerT / 2) + j];
+    int tot = 0;
+#pragma unroll
+    for (int j = 0; j < kPerT / 2; ++j) tot += static_cast<int>((wv[j] & 0xffffu) + (wv[j] >> 16));
+    const int lane64 = t & 63;
+    int incl = tot;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int v = __shfl_up(incl, d, 64);
+        if (lane64 >= d) incl += v;
+    }
+    if (lane64 == 63) wtot[t >> 6] = incl;
+    lds_barrier();
+    int run = incl - tot;
+    for (int q = 0; q < (t >> 6); ++q) run += wtot[q];
+#pragma unroll
+    for (int j = 0; j < kPerT / 2; ++j) {
+        const uint32_t lo = static_cast<uint32_t>(run);
+        run += static_cast<int>(wv[j] & 0xffffu);
+        const uint32_t hi = static_cast<uint32_t>(run);
+        run += static_cast<int>(wv[j] >> 16);
+        tbw[t * (kPerT / 2) + j] = lo | (hi << 16);
+    }
+    if (t == kThreads - 1) reinterpret_cast<uint16_t*>(tbw)[kBuckets] = static_cast<uint16_t>(run);
+    lds_barrier();
     return bm;
+}
+
+// Clears the bucket counters of tbw (before the barrier that precedes
+// place_in_window).  Called by every thread of the workgroup.
+__device__ __forceinline__ void clear_buckets(uint32_t* tbw) {
+    static_assert(kBuckets / 2 == kThreads * 4, "one 16-byte store per thread");
+    reinterpret_cast<uint4*>(tbw)[threadIdx.x] = make_uint4(0u, 0u, 0u, 0u);
 }
 
 // Places this thread's sorted values x[next..nmine) that end in a window of
@@ -1225,15 +1264,16 @@ __device__ __forceinline__ WinBuckets build_buckets(const double* sw, int nwin, 
 // bisection of that range finds it; the ranges of kPlaceGroup values are
 // bisected together, so their LDS reads are in flight at once.
 // res[q] = base + position; next moves past the values placed.  Called by
-// every thread of the workgroup (the table is built here); tb holds
-// kBuckets + 1 entries of LDS.
-__device__ __forceinline__ void place_in_window(const double* sw, uint16_t* tb, int nwin,
+// every thread of the workgroup (the table is built here, in tbw: see
+// build_buckets, its counters cleared by clear_buckets before the barrier
+// that precedes this call).
+__device__ __forceinline__ void place_in_window(const double* sw, uint32_t* tbw, int nwin,
                                                 bool final_window,
                                                 const double (&x)[kDensePer], int nmine,
                                                 int64_t base, int& next,
                                                 int32_t (&res)[kDensePer]) {
-    const WinBuckets bm = build_buckets(sw, nwin, tb);
-    lds_barrier();
+    const WinBuckets bm = build_buckets(sw, nwin, tbw);
+    const uint16_t* tb = reinterpret_cast<const uint16_t*>(tbw);
     const double wend = sw[nwin - 1];
     int nxt = next;
 #pragma unroll
@@ -1376,7 +1416,7 @@ __device__ __forceinline__ void k_map_dense_body(Src w, WArgs wa, ZArgs za, Shar
     // lane-chunk totals of its rows
     __shared__ double sw[kWinLen];
     __shared__ double ltot[kThreads];
-    __shared__ uint16_t tb[kBuckets + 1];
+    __shared__ __attribute__((aligned(16))) uint32_t tbw[(kBuckets + 2) / 2];
     const int t = threadIdx.x;
     const int64_t N = za.N;
     const int64_t c0 = static_cast<int64_t>(blockIdx.x) * per_wg;
@@ -1439,6 +1479,7 @@ __device__ __forceinline__ void k_map_dense_body(Src w, WArgs wa, ZArgs za, Shar
     // window entries 16t .. 16t+15, then the draws that end in it are placed
     auto window = [&](const WinRowLoad<Elem>& L, int64_t ws0) {
         const int nw = static_cast<int>((gs1 - ws0 + 1 < kWinSub) ? gs1 - ws0 + 1 : kWinSub);
+        clear_buckets(tbw);
         {
             double pt = L.rc.at(0);
 #pragma unroll
@@ -1461,7 +1502,7 @@ __device__ __forceinline__ void k_map_dense_body(Src w, WArgs wa, ZArgs za, Shar
         // entries of the window that exist
         const int64_t wlen64 = wa.M - ws0 * kSub;
         const int nwin = (nw * kSub < wlen64) ? nw * kSub : static_cast<int>(wlen64);
-        place_in_window(sw, tb, nwin, false, us, nmine, ws0 * kSub, next, res);
+        place_in_window(sw, tbw, nwin, false, us, nmine, ws0 * kSub, next, res);
         lds_barrier();   // ltot, the window and its table are rewritten by the next window
     };
     window(cur, gs0);   // the loads made before the uniforms
@@ -1835,7 +1876,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     const double* __restrict__ W, int64_t M, const double* __restrict__ u, int64_t N,
     int32_t* __restrict__ r, int per_wg) {
     __shared__ double sw[kWinLen];
-    __shared__ uint16_t tb[kBuckets + 1];
+    __shared__ __attribute__((aligned(16))) uint32_t tbw[(kBuckets + 2) / 2];
     __shared__ int64_t range[2];
     const int t = threadIdx.x;
     const int64_t c0 = static_cast<int64_t>(blockIdx.x) * per_wg;
@@ -1858,8 +1899,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     for (int64_t ws0 = lo; ws0 <= hi; ws0 += kWinLen) {
         const int nwin = static_cast<int>((hi + 1 - ws0 < kWinLen) ? hi + 1 - ws0 : kWinLen);
         for (int k = t; k < nwin; k += kThreads) sw[k] = W[ws0 + k];
+        clear_buckets(tbw);
         lds_barrier();
-        place_in_window(sw, tb, nwin, ws0 + kWinLen > hi, x, nmine, ws0, next, res);
+        place_in_window(sw, tbw, nwin, ws0 + kWinLen > hi, x, nmine, ws0, next, res);
         lds_barrier();   // the window is rewritten next
     }
     if (nmine == kDensePer && (reinterpret_cast<uintptr_t>(r + iu0) & 15) == 0) {
