@@ -123,12 +123,36 @@ __device__ __forceinline__ void reduce_z_block(const ZArgs& za, int64_t g, doubl
         double zr[kLane];
 #pragma unroll
         for (int k = 0; k < kLane; ++k) zr[k] = sigma + (c + p[k]);
-        if (nv == kLane) {
-            f64x2* q = reinterpret_cast<f64x2*>(za.zrel + i0);
+        // the block's prefixes leave through LDS, half a block (8 rows) at a
+        // time, as coalesced 16-byte pieces with the non-temporal policy; a
+        // thread's 16 values sit 17 doubles apart there (fewer bank conflicts)
+        constexpr int kHalfThreads = kThreads / 2;
+        constexpr int kPad = kLane + 1;
+        double* stage = lane_tot;   // kHalfThreads * kPad doubles
+        const int64_t blk = g * kZBlock;
+        const int64_t lim = (za.N + 1 - blk < kZBlock) ? za.N + 1 - blk : kZBlock;   // prefixes of the block
 #pragma unroll
-            for (int v = 0; v < kLane / 2; ++v) q[v] = f64x2{zr[2 * v], zr[2 * v + 1]};
-        } else {
-            for (int k = 0; k < nv; ++k) za.zrel[i0 + k] = zr[k];
+        for (int h = 0; h < 2; ++h) {
+            lds_barrier();   // every read of the region before it is done
+            if (t / kHalfThreads == h) {
+                const int tl = t % kHalfThreads;
+#pragma unroll
+                for (int k = 0; k < kLane; ++k) stage[tl * kPad + k] = zr[k];
+            }
+            lds_barrier();
+#pragma unroll
+            for (int m = 0; m < kHalfThreads * kLane / 2 / kThreads; ++m) {
+                const int pc = t + m * kThreads;          // piece of the half
+                const int e = 2 * pc;                     // its first value in the half
+                const int at = (e / kLane) * kPad + (e % kLane);
+                const int64_t j = static_cast<int64_t>(h) * kHalfThreads * kLane + e;   // in the block
+                const double a = stage[at], b = stage[at + 1];
+                if (j + 1 < lim) {
+                    __builtin_nontemporal_store(f64x2{a, b}, reinterpret_cast<f64x2*>(za.zrel + blk + j));
+                } else if (j < lim) {
+                    za.zrel[blk + j] = a;
+                }
+            }
         }
         if (t == 0) za.blk_tot[g] = total;
     }
