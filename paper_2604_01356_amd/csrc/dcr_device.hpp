@@ -204,6 +204,7 @@ __device__ __forceinline__ RawChunk<Tin> load_raw_any(const Tin* __restrict__ p)
 // vector type has element alignment: a filter of a batch may start at any
 // element, and global memory accepts element-aligned vector loads here.
 typedef float f32x4_ea __attribute__((ext_vector_type(4), aligned(4)));
+typedef double f64x2_ea __attribute__((ext_vector_type(2), aligned(8)));
 constexpr int kCachePolicyNT = 2;   // non-temporal bit of the cache-policy operand
 
 // A chunk of which only the first n values exist (n <= 0: none; nothing is

@@ -61,7 +61,10 @@ template <typename Tin>
 struct ReduceSmem {
     static constexpr int kBuf = (sizeof(Tin) == 4) ? kWaves * kWaveRoundF32 * 4 : 16;
     static constexpr int kEpi = (kWIters * kThreads + 2 * kWSubPerBlock) * 8;
-    static constexpr int kBuf0 = kBuf > kEpi ? kBuf : kEpi;
+    // binary64: one round of weights staged per wave (4 waves x 8 KB)
+    static constexpr int kStage = (sizeof(Tin) == 8) ? kThreads * kLane * 8 : 0;
+    static constexpr int kBuf0a = kBuf > kEpi ? kBuf : kEpi;
+    static constexpr int kBuf0 = kBuf0a > kStage ? kBuf0a : kStage;
 };
 
 // s_waitcnt lgkmcnt(0) with vmcnt and expcnt left at their maxima
@@ -312,24 +315,57 @@ __device__ __forceinline__ void reduce_w_block(const Tin* __restrict__ w, const 
             bad = (mn < 0.0f) ? 1 : 0;
         }
     }
-    if (full && !done) {
-        // binary64: lane-strided vector loads (element-aligned), the next
-        // round issued before summing.  These stay cached: each lane reads its
-        // own 128-byte line in eight pieces, and non-temporal loads would send
-        // every piece to memory (measured 2.5 times slower)
-        const Tin* base = w + blk0 + row * kSub + lane * kLane;
-        Tin mn = static_cast<Tin>(0);
-        RawChunk<Tin> cur = load_raw_any<Tin>(base);
-        mn = cur.raw(0);
+    if constexpr (sizeof(Tin) == 8) {
+        if (full) {
+            // binary64: each wave loads its quarter of a round (1024 weights,
+            // its four rows) as coalesced 16-byte non-temporal pieces of
+            // element-aligned addresses, one round ahead in registers, and
+            // passes them through its own 8 KB of LDS into the lane-chunk
+            // layout.  Piece j of lane chunk c sits at slot j ^ (c & 7) of the
+            // chunk's 128 bytes, so that neither the wave's writes (eight
+            // lanes per chunk) nor its reads (one chunk per lane) meet in a
+            // bank.  (Cached lane-strided loads, each lane reading its own
+            // line, streamed at about 5.4 TB/s; non-temporal, each 16-byte
+            // piece went to memory on its own.)
+            done = true;
+            constexpr int kWaveRound = kRows / kWaves * kSub;   // 1024 weights
+            constexpr int kPieces = kWaveRound / 2 / 64;         // 16-byte pieces per lane
+            constexpr int kDepth = 1;
+            const int wv = t >> 6;
+            const int l64 = t & 63;
+            const double* src = reinterpret_cast<const double*>(w) + blk0 + wv * kWaveRound;
+            f64x2* const region = reinterpret_cast<f64x2*>(sb0) + wv * (kWaveRound / 2);
+            f64x2 ring[kDepth + 1][kPieces];
+            auto fetch = [&](int it, f64x2 (&dst)[kPieces]) {
+                const double* g0 = src + it * (kWaves * kWaveRound);
 #pragma unroll
-        for (int it = 0; it < kWIters; ++it) {
-            RawChunk<Tin> nxt;
-            if (it + 1 < kWIters) nxt = load_raw_any<Tin>(base + (it + 1) * kRows * kSub);
-            lt[it] = raw_sum<Tin>(cur, mn);
-            if (it + 1 < kWIters) cur = nxt;
-            __builtin_amdgcn_sched_barrier(0);
+                for (int k = 0; k < kPieces; ++k)
+                    dst[k] = __builtin_nontemporal_load(
+                        reinterpret_cast<const f64x2_ea*>(g0 + 2 * (k * 64 + l64)));
+            };
+#pragma unroll
+            for (int it = 0; it < kDepth; ++it) fetch(it, ring[it]);
+            double mn = 0.0;
+#pragma unroll
+            for (int it = 0; it < kWIters; ++it) {
+                if (it + kDepth < kWIters) fetch(it + kDepth, ring[(it + kDepth) % (kDepth + 1)]);
+#pragma unroll
+                for (int k = 0; k < kPieces; ++k) {
+                    const int pc = k * 64 + l64;   // piece of the wave's round
+                    const int c = pc >> 3, j = pc & 7;
+                    region[c * 8 + (j ^ (c & 7))] = ring[it % (kDepth + 1)][k];
+                }
+                __builtin_amdgcn_s_waitcnt(kWaitLdsOnly);   // the wave's writes are done
+                __builtin_amdgcn_wave_barrier();
+                RawChunk<double> rc;   // lane l64 holds chunk l64 of the wave's round
+#pragma unroll
+                for (int j = 0; j < kLane / 2; ++j) rc.v[j] = region[l64 * 8 + (j ^ (l64 & 7))];
+                if (it == 0) mn = rc.raw(0);
+                lt[it] = raw_sum<double>(rc, mn);
+                __builtin_amdgcn_wave_barrier();   // the region is rewritten next round
+            }
+            bad = (mn < 0.0) ? 1 : 0;
         }
-        bad = (mn < static_cast<Tin>(0)) ? 1 : 0;
     }
     if (!full) {
         // the array's ragged last block: the same lane-strided loop, each chunk
@@ -827,7 +863,7 @@ __device__ __forceinline__ void k_materialize_w_body(Src w, WArgs wa, SharedArgs
         const f64x2* st = reinterpret_cast<const f64x2*>(stage);
         f64x2* q = reinterpret_cast<f64x2*>(W + round0);
 #pragma unroll
-        for (int m = 0; m < kLane / 2; ++m) q[t + m * kThreads] = st[t + m * kThreads];
+        for (int m = 0; m < kLane / 2; ++m) __builtin_nontemporal_store(st[t + m * kThreads], &q[t + m * kThreads]);
     } else {
         for (int k = 0; k < nv; ++k) W[j0 + k] = out[k];
     }
