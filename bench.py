@@ -238,6 +238,42 @@ def measure_copy_bw(dcr, torch, dev, reps: int = 10) -> dict:
     return res
 
 
+def measure_read_same_bytes(dcr, torch, dev, nbytes: int, reps: int = 10) -> dict:
+    """The library's streaming read (both patterns, the same sweep as
+    measure_copy_bw) over as many bytes as the dominant kernel moves: a launch
+    of a few hundred MB carries its own ramp and tail, which 1 GiB hides."""
+    import statistics
+    n = max(16, nbytes // 16 * 16) // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    part = torch.empty(16384, dtype=torch.float32, device=dev)
+
+    def med(fn):
+        for _ in range(2):
+            fn()
+        times = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1) * 1e-3)
+        return statistics.median(times)
+
+    res = {"bytes": 4 * n, "read_gbs": 0.0}
+    for unroll in (4, 8, 16):
+        for grid in (1024, 2048, 4096, 8192, 16384):
+            for kind, name in ((0, "grid-stride"), (2, "contiguous runs, non-temporal")):
+                t = med(lambda: dcr.dcr_stream_probe(kind, src, part, grid, unroll))
+                if 4 * n / t / 1e9 > res["read_gbs"]:
+                    res["read_gbs"] = 4 * n / t / 1e9
+                    res["read_launch"] = [name, grid, unroll]
+    del src, part
+    torch.cuda.empty_cache()
+    return res
+
+
 def batched_reduce_bytes(w_off, n_off, s_w: int) -> int:
     """Algorithmic HBM bytes of the batched reduce launch: every filter's
     weights once, its sub-tile ends and block totals, its N_b + 1 spacing
@@ -743,6 +779,7 @@ def main():
         raise SystemExit(f"bench.py: no byte model for the launch kind {dom}")
     achieved = dom_bytes / (kernels[dom] * 1e-3) / 1e9
     traffic = load_traffic(args.workload, args.precision, dom)
+    read_same = measure_read_same_bytes(dcr, torch, dev, dom_bytes)
     out = {
         "metric": METRIC,
         "value": wl.N / (ms * 1e-3),
@@ -780,8 +817,10 @@ def main():
             "avg_launch_us": kernels[dom] * 1e3,
             "frac_of_copy": achieved / copy_bw["copy_gbs"],
             "frac_of_read": achieved / copy_bw["read_gbs"],
+            "frac_of_read_same_bytes": achieved / read_same["read_gbs"],
         },
         "device_copy_bw": copy_bw,
+        "device_read_same_bytes": read_same,
     }
     if not args.no_compare:
         other = "f64" if args.precision == "f32" else "f32"

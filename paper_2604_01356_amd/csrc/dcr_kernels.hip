@@ -1234,6 +1234,14 @@ constexpr int kWinLen = kWinSub * kSub;       // weights per window (= kThreads 
 constexpr int kMaxWin = 4;
 static_assert(kWinLen <= kBetaLds, "the window reuses the block-end stage");
 
+// LDS slot of window entry i: within each group of 16 entries (the 16 a
+// thread writes when it fills the window) the slots are rotated by the group's
+// index, so that the 64 lanes of a wave writing their k-th entries spread over
+// the banks instead of meeting in one.
+__device__ __forceinline__ int win_slot(int i) {
+    return (i & ~(kLane - 1)) | ((i & (kLane - 1)) ^ ((i / kLane) & (kLane - 1)));
+}
+
 // Bucket index of a window of non-decreasing values: with lo the first value
 // and hi the last, bucket(x) = floor((x - lo) * kBuckets / (hi - lo)) clamped
 // to 0..kBuckets-1 (0 everywhere when the window has no width).  Every step
@@ -1267,15 +1275,15 @@ __device__ __forceinline__ WinBuckets build_buckets(const double* sw, int nwin, 
     static_assert(kBuckets % kThreads == 0 && kPerT % 2 == 0, "bucket words per thread");
     __shared__ int wtot[kThreads / 64];
     WinBuckets bm;
-    bm.lo = sw[0];
-    const double width = sw[nwin - 1] - bm.lo;
+    bm.lo = sw[win_slot(0)];
+    const double width = sw[win_slot(nwin - 1)] - bm.lo;
     double sc = (width > 0.0) ? static_cast<double>(kBuckets) / width : 0.0;
     if (!(sc <= 1.0e300)) sc = 0.0;
     bm.scale = sc;
     const int n = nwin - 1;
     const int t = threadIdx.x;
     for (int i = t; i < n; i += kThreads) {
-        const int bi = bm.of(sw[i]);
+        const int bi = bm.of(sw[win_slot(i)]);
         atomicAdd(&tbw[bi >> 1], (bi & 1) ? 0x10000u : 1u);
     }
     lds_barrier();
@@ -1317,7 +1325,8 @@ __device__ __forceinline__ void clear_buckets(uint32_t* tbw) {
 }
 
 // Places this thread's sorted values x[next..nmine) that end in a window of
-// nwin non-decreasing values sw (those not above the window's last value, or
+// nwin non-decreasing values (entry i at sw[win_slot(i)]; those not above the
+// window's last value, or
 // all that remain in the final window): each one's position is the count of
 // window entries below it among the first nwin-1.  For a value v in bucket b
 // that count lies in [tb[b], tb[b+1]] (the monotone bucket map), and a
@@ -1334,7 +1343,7 @@ __device__ __forceinline__ void place_in_window(const double* sw, uint32_t* tbw,
                                                 int32_t (&res)[kDensePer]) {
     const WinBuckets bm = build_buckets(sw, nwin, tbw);
     const uint16_t* tb = reinterpret_cast<const uint16_t*>(tbw);
-    const double wend = sw[nwin - 1];
+    const double wend = sw[win_slot(nwin - 1)];
     int nxt = next;
 #pragma unroll
     for (int g = 0; g < kDensePer; g += kPlaceGroup) {
@@ -1358,7 +1367,7 @@ __device__ __forceinline__ void place_in_window(const double* sw, uint32_t* tbw,
 #pragma unroll
                 for (int k = 0; k < kPlaceGroup; ++k) m[k] = (a[k] + e[k]) >> 1;
 #pragma unroll
-                for (int k = 0; k < kPlaceGroup; ++k) sv[k] = sw[m[k]];
+                for (int k = 0; k < kPlaceGroup; ++k) sv[k] = sw[win_slot(m[k])];
                 bool more = false;
 #pragma unroll
                 for (int k = 0; k < kPlaceGroup; ++k) {
@@ -1556,7 +1565,7 @@ __device__ __forceinline__ void k_map_dense_body(Src w, WArgs wa, ZArgs za, Shar
         for (int k = 0; k < kLane; ++k) {
             pk = (k == 0) ? L.rc.at(0) : pk + L.rc.at(k);
             const double S = block_end_at(L.sigma + (c + pk), L.X, L.beta_b, L.beta_n);
-            sw[t * kLane + k] = (k < L.nv) ? S / total : __builtin_huge_val();
+            sw[win_slot(t * kLane + k)] = (k < L.nv) ? S / total : __builtin_huge_val();
         }
         lds_barrier();
         // entries of the window that exist
@@ -1958,7 +1967,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     int next = 0;
     for (int64_t ws0 = lo; ws0 <= hi; ws0 += kWinLen) {
         const int nwin = static_cast<int>((hi + 1 - ws0 < kWinLen) ? hi + 1 - ws0 : kWinLen);
-        for (int k = t; k < nwin; k += kThreads) sw[k] = W[ws0 + k];
+        for (int k = t; k < nwin; k += kThreads) sw[win_slot(k)] = W[ws0 + k];
         clear_buckets(tbw);
         lds_barrier();
         place_in_window(sw, tbw, nwin, ws0 + kWinLen > hi, x, nmine, ws0, next, res);
@@ -2201,12 +2210,17 @@ constexpr int kSegBetaLds = 128;             // block ends kept in LDS (sampled 
 constexpr int kSegSubBlocks = 4;             // blocks whose sub-tile ends are staged
 constexpr int kSegDraws = 1;                 // draws per thread in flight at the element level
 
+// A touched sub-tile's 16 chunk values in LDS take 17 slots: with a row of
+// exactly 16 doubles every thread of a wave walking its own row met the
+// others in the same bank.
+constexpr int kCrunStride = kRowLanes + 1;
+
 template <int kSegU, int kSegPass>
 struct SegLds {
     double sx[kSegU];                                  // thresholds, in draw order
     double sbeta[kSegBetaLds];
     double ssub[kSegSubBlocks * kWSubPerBlock];
-    double crun[kSegPass * kRowLanes];                 // chunk totals, then running sums
+    double crun[kSegPass * kCrunStride];               // chunk totals, then running sums
     int32_t sid[kSegU];                                // sub-tile of each draw, then r
     int16_t srank[kSegU];                              // rank of each draw's sub-tile
     int32_t lsub[kSegU];                               // touched sub-tiles
@@ -2439,7 +2453,7 @@ __device__ void map_seg_chunk(const Tin* __restrict__ w, const WArgs& wa, const 
         if (wa.chunk_tot) {
 #pragma unroll 4
             for (int k = p0 + row; k < p1; k += kRows)
-                L.crun[(k - p0) * kRowLanes + lane] =
+                L.crun[(k - p0) * kCrunStride + lane] =
                     wa.chunk_tot[static_cast<int64_t>(L.lsub[k]) * kRowLanes + lane];
         } else {
 #pragma unroll 4
@@ -2456,7 +2470,7 @@ __device__ void map_seg_chunk(const Tin* __restrict__ w, const WArgs& wa, const 
             double cs = rc.at(0);
 #pragma unroll
             for (int q = 1; q < kLane; ++q) cs = cs + rc.at(q);
-            L.crun[(k - p0) * kRowLanes + lane] = cs;
+            L.crun[(k - p0) * kCrunStride + lane] = cs;
         }
         }
         lds_barrier();
@@ -2465,8 +2479,8 @@ __device__ void map_seg_chunk(const Tin* __restrict__ w, const WArgs& wa, const 
             double run = 0.0;
 #pragma unroll
             for (int l = 0; l < kRowLanes; ++l) {
-                run = run + L.crun[t * kRowLanes + l];
-                L.crun[t * kRowLanes + l] = run;
+                run = run + L.crun[t * kCrunStride + l];
+                L.crun[t * kCrunStride + l] = run;
             }
         }
         lds_barrier();
@@ -2497,7 +2511,7 @@ __device__ void map_seg_chunk(const Tin* __restrict__ w, const WArgs& wa, const 
                 bn[m] = beta_end(b);
                 sg[m] = sigma_of(b, s);
                 bx[m] = sigma_of(b, kWSubPerBlock);   // the block total
-                cr[m] = L.crun + (k - p0) * kRowLanes;
+                cr[m] = L.crun + (k - p0) * kCrunStride;
                 j0[m] = sub0;
                 nv[m] = slen;
                 lc[m] = 0;
