@@ -60,10 +60,13 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32
                                                 uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
-        const uint32_t lo_a = 0xD2511F53u * c0;
-        const uint32_t hi_a = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo_b = 0xCD9E8D57u * c2;
-        const uint32_t hi_b = __umulhi(0xCD9E8D57u, c2);
+        // each product's two halves from one 32 x 32 -> 64 multiply
+        const uint64_t pa = static_cast<uint64_t>(0xD2511F53u) * c0;
+        const uint64_t pb = static_cast<uint64_t>(0xCD9E8D57u) * c2;
+        const uint32_t lo_a = static_cast<uint32_t>(pa);
+        const uint32_t hi_a = static_cast<uint32_t>(pa >> 32);
+        const uint32_t lo_b = static_cast<uint32_t>(pb);
+        const uint32_t hi_b = static_cast<uint32_t>(pb >> 32);
         const uint32_t n0 = hi_b ^ c1 ^ k0;
         const uint32_t n2 = hi_a ^ c3 ^ k1;
         c0 = n0;

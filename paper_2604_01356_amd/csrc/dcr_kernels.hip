@@ -60,7 +60,8 @@ constexpr int kWaves = kThreads / 64;
 template <typename Tin>
 struct ReduceSmem {
     static constexpr int kBuf = (sizeof(Tin) == 4) ? kWaves * kWaveRoundF32 * 4 : 16;
-    static constexpr int kEpi = (kWIters * kThreads + 2 * kWSubPerBlock) * 8;
+    // the epilogue: lane totals in rows of 16 padded to 17, then sub-tile totals and ends
+    static constexpr int kEpi = (kWIters * (kThreads + kThreads / kRowLanes) + 2 * kWSubPerBlock) * 8;
     // binary64: one round of weights staged per wave (4 waves x 8 KB)
     static constexpr int kStage = (sizeof(Tin) == 8) ? kThreads * kLane * 8 : 0;
     static constexpr int kBuf0a = kBuf > kEpi ? kBuf : kEpi;
@@ -170,8 +171,12 @@ __device__ __forceinline__ void reduce_z_block(const ZArgs& za, int64_t g, doubl
 // sub-tile ends and the block total.  sb0 is at least ReduceSmem<>::kEpi bytes.
 __device__ __forceinline__ void reduce_w_epilogue(const double (&lt)[kWIters], int bad,
                                                   const WArgs& wa, int64_t b, unsigned char* sb0) {
-    double* lane_tot = reinterpret_cast<double*>(sb0);   // [kWIters][kThreads]
-    double* sub_tot = lane_tot + kWIters * kThreads;      // [kWSubPerBlock]
+    // lane totals: round it, thread t at it * kEpiRow + 17 * row + lane (a
+    // sub-tile's 16 totals are read by one thread; rows of 16 doubles put the
+    // 64 readers of a wave in one bank)
+    constexpr int kEpiRow = kThreads + kThreads / kRowLanes;
+    double* lane_tot = reinterpret_cast<double*>(sb0);   // [kWIters][kEpiRow]
+    double* sub_tot = lane_tot + kWIters * kEpiRow;       // [kWSubPerBlock]
     double* sub_end = sub_tot + kWSubPerBlock;            // [kWSubPerBlock]
     const int t = threadIdx.x;
     if (wa.chunk_tot) {
@@ -185,12 +190,12 @@ __device__ __forceinline__ void reduce_w_epilogue(const double (&lt)[kWIters], i
     }
     lds_barrier();   // the first stream buffer becomes the epilogue's scratch
 #pragma unroll
-    for (int it = 0; it < kWIters; ++it) lane_tot[it * kThreads + t] = lt[it];
+    for (int it = 0; it < kWIters; ++it) lane_tot[it * kEpiRow + t + t / kRowLanes] = lt[it];
     bad = block_any(bad);
     if (t < kWSubPerBlock) {
         const int it = t / kRows;
         const int r = t % kRows;
-        const double* p = lane_tot + it * kThreads + r * kRowLanes;
+        const double* p = lane_tot + it * kEpiRow + r * (kRowLanes + 1);
         double lv[kRowLanes];
 #pragma unroll
         for (int l = 0; l < kRowLanes; ++l) lv[l] = p[l];
