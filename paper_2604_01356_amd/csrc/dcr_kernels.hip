@@ -1495,33 +1495,22 @@ __device__ __forceinline__ void k_map_dense_body(Src w, WArgs wa, ZArgs za, Shar
     const int64_t N = za.N;
     const int64_t c0 = static_cast<int64_t>(blockIdx.x) * per_wg;
     const int64_t c1 = (c0 + per_wg < N) ? c0 + per_wg : N;
-    const bool ok = sh.status[0] == kStatusOk;
-    const double total = sh.totals[0];
-    const double ztot = sh.totals[1];
     const int64_t iu0 = c0 + static_cast<int64_t>(t) * kDensePer;
     const int nmine = clamp_count(c1 - iu0, kDensePer);
-    if (!ok) {
-        for (int q = 0; q < nmine; ++q) r[iu0 + q] = -1;
-        return;
-    }
-    // the chunk's span of sub-tiles; a span wider than kMaxWin windows takes
-    // one quad search per uniform instead (map_wide_chunk)
+    // every load whose address is known at the start goes out together: the
+    // status, the totals, the chunk's span, and this thread's in-block spacing
+    // prefixes and spacing block ends (its 16 draws lie in one spacing block:
+    // 16 divides 4096 and per_wg).  All lie in the workspace whatever the
+    // status says; nothing is used before the status is checked.
+    const int status = sh.status[0];
+    const double total = sh.totals[0];
+    const double ztot = sh.totals[1];
     const int64_t gs0 = span[2 * static_cast<int64_t>(blockIdx.x)];
     const int64_t gs1 = span[2 * static_cast<int64_t>(blockIdx.x) + 1];
-    const bool is_wide = gs1 - gs0 + 1 > static_cast<int64_t>(kWinSub) * kMaxWin;
-    const int row = t / kRowLanes;
-    const int lane = t % kRowLanes;
-    // the first window's loads go out before the uniforms are formed
-    WinRowLoad<Elem> cur{};
-    if (!is_wide) cur = window_row_load(w, wa, gs0, gs1, row, lane);
-    // this thread's 16 draws lie in one spacing block (16 divides 4096 and
-    // per_wg): load their in-block prefixes at once, then form the uniforms
-    double us[kDensePer];
     const bool spacings = za.scheme == kSchemeMultinomial;
-    if (!spacings) {
-#pragma unroll
-        for (int q = 0; q < kDensePer; ++q) us[q] = (q < nmine) ? scheme_uniform(za, iu0 + q) : 0.0;
-    } else {
+    double us[kDensePer];
+    double zb = 0.0, zn = 0.0;
+    if (spacings) {
         if (nmine == kDensePer) {
             const f64x2* q2 = reinterpret_cast<const f64x2*>(za.zrel + iu0);
 #pragma unroll
@@ -1535,8 +1524,25 @@ __device__ __forceinline__ void k_map_dense_body(Src w, WArgs wa, ZArgs za, Shar
             for (int q = 0; q < kDensePer; ++q) us[q] = (q < nmine) ? za.zrel[iu0 + q] : 0.0;
         }
         const int64_t gz = iu0 / kZBlock;
-        const double zb = (gz == 0) ? 0.0 : za.beta[gz - 1];
-        const double zn = za.beta[gz < za.nb ? gz : za.nb - 1];
+        zb = (gz == 0) ? 0.0 : za.beta[gz - 1];
+        zn = za.beta[gz < za.nb ? gz : za.nb - 1];
+    }
+    if (status != kStatusOk) {
+        for (int q = 0; q < nmine; ++q) r[iu0 + q] = -1;
+        return;
+    }
+    // a span wider than kMaxWin windows takes one quad search per uniform
+    // instead (map_wide_chunk)
+    const bool is_wide = gs1 - gs0 + 1 > static_cast<int64_t>(kWinSub) * kMaxWin;
+    const int row = t / kRowLanes;
+    const int lane = t % kRowLanes;
+    // the first window's loads go out before the uniforms are formed
+    WinRowLoad<Elem> cur{};
+    if (!is_wide) cur = window_row_load(w, wa, gs0, gs1, row, lane);
+    if (!spacings) {
+#pragma unroll
+        for (int q = 0; q < kDensePer; ++q) us[q] = (q < nmine) ? scheme_uniform(za, iu0 + q) : 0.0;
+    } else {
 #pragma unroll
         for (int q = 0; q < kDensePer; ++q) us[q] = uniform_of(us[q], iu0 + q, N, zb, zn, ztot);
     }
