@@ -237,10 +237,8 @@ __device__ __forceinline__ void reduce_w_block(const Tin* __restrict__ w, const 
     double lt[kWIters];
     const bool full = blk0 + kWBlock <= wa.M;
     const bool aligned = (vec_ok & 1) != 0;
-    bool done = false;
     if constexpr (sizeof(Tin) == 4) {
         if (full && aligned) {
-            done = true;
             float* const bufs[3] = {reinterpret_cast<float*>(sb0), reinterpret_cast<float*>(sb1),
                                     reinterpret_cast<float*>(sb2)};
             const int wv = t >> 6;
@@ -285,7 +283,6 @@ __device__ __forceinline__ void reduce_w_block(const Tin* __restrict__ w, const 
             // coalesced 16-byte pieces of element-aligned addresses, two
             // rounds ahead in registers, and passes them through its own LDS
             // region into the lane-chunk layout of the path above
-            done = true;
             const int wv = t >> 6;
             const int l64 = t & 63;
             const float* src = reinterpret_cast<const float*>(w) + blk0 + wv * kWaveRoundF32;
@@ -332,7 +329,6 @@ __device__ __forceinline__ void reduce_w_block(const Tin* __restrict__ w, const 
             // bank.  (Cached lane-strided loads, each lane reading its own
             // line, streamed at about 5.4 TB/s; non-temporal, each 16-byte
             // piece went to memory on its own.)
-            done = true;
             constexpr int kWaveRound = kRows / kWaves * kSub;   // 1024 weights
             constexpr int kPieces = kWaveRound / 2 / 64;         // 16-byte pieces per lane
             constexpr int kDepth = 1;
@@ -1780,7 +1776,75 @@ __device__ __forceinline__ void reduce_z_block_quads(const ZArgs& za, int64_t g,
 // layout q = t / 256 sums the lane chunks of rounds q and q + 4, both loaded
 // at once; then k_reduce's epilogue (sub-tile totals, the chain of sub-tile
 // ends, the block total; NaN for a block holding an inadmissible weight).
-// All threads call it; lds holds 2048 + 256 doubles.
+// All threads call it; lds holds kSmallLds doubles.
+constexpr int kSmallLds = kSmallThreads / 64 * 256;   // 2 KB of staging per wave
+static_assert(kSmallLds >= kWIters * kThreads + 2 * kWSubPerBlock, "the epilogue's LDS");
+
+// Lane chunks of two 1024-weight ranges of a block (the wave's chunks of two
+// rounds; range r holds n[r] weights, the rest read as zeros), for the 64
+// lanes of a wave: every piece is loaded first, as
+// coalesced 16-byte pieces of element-aligned addresses (a lane-strided load
+// touches 64 cache lines per instruction, and one CU issues them all), then a
+// quarter (binary64) or half (binary32) of a range at a time passes through
+// the wave's 2 KB of LDS to the lanes owning its chunks, each chunk's pieces
+// rotated by the chunk's index against bank conflicts.  tsum[r] = the left-
+// to-right sum of the lane's chunk of range r; mn (0 on entry) falls to the
+// smallest weight seen when one is negative.
+template <typename Elem>
+__device__ __forceinline__ void wide_chunk_sums(const Elem* __restrict__ r0, const Elem* __restrict__ r1,
+                                                const int (&n)[2], double* stage, double (&tsum)[2],
+                                                Elem& mn) {
+    typedef Elem piece_t __attribute__((ext_vector_type(16 / sizeof(Elem))));
+    typedef Elem piece_ea __attribute__((ext_vector_type(16 / sizeof(Elem)), aligned(sizeof(Elem))));
+    constexpr int kPer = 16 / sizeof(Elem);          // elements per piece
+    constexpr int kCP = kLane / kPer;                // pieces per chunk (8 or 4)
+    constexpr int kLoads = kLane * 64 / kPer / 64;   // pieces per lane per range (8 or 4)
+    constexpr int kStep = 2;                         // loads per pass through LDS (128 pieces)
+    constexpr int kOwners = kStep * 64 / kCP;        // lanes served per pass (16 or 32)
+    const int l64 = threadIdx.x & 63;
+    piece_t pc[2][kLoads];
+    const Elem* const rr[2] = {r0, r1};
+#pragma unroll
+    for (int rg = 0; rg < 2; ++rg) {
+#pragma unroll
+        for (int k = 0; k < kLoads; ++k) {
+            const int e0 = (k * 64 + l64) * kPer;   // the piece's first element
+            if (e0 + kPer <= n[rg]) {
+                pc[rg][k] = *reinterpret_cast<const piece_ea*>(rr[rg] + e0);
+            } else {
+                piece_t v = {};
+#pragma unroll
+                for (int i = 0; i < kPer; ++i)
+                    if (e0 + i < n[rg]) v[i] = rr[rg][e0 + i];
+                pc[rg][k] = v;
+            }
+        }
+    }
+    piece_t* const st = reinterpret_cast<piece_t*>(stage);   // 128 pieces
+#pragma unroll
+    for (int rg = 0; rg < 2; ++rg) {
+#pragma unroll
+        for (int s0 = 0; s0 < kLoads; s0 += kStep) {
+#pragma unroll
+            for (int k = s0; k < s0 + kStep; ++k) {
+                const int pl = (k - s0) * 64 + l64;   // piece of this pass
+                const int c = pl / kCP, j = pl % kCP;
+                st[c * kCP + (j ^ (c & (kCP - 1)))] = pc[rg][k];
+            }
+            __builtin_amdgcn_s_waitcnt(kWaitLdsOnly);   // the wave's writes are done
+            __builtin_amdgcn_wave_barrier();
+            const int c = l64 - (s0 / kStep) * kOwners;   // this lane's chunk in the pass
+            if (c >= 0 && c < kOwners) {
+                RawChunk<Elem> rc;
+#pragma unroll
+                for (int j = 0; j < kCP; ++j) rc.v[j] = st[c * kCP + (j ^ (c & (kCP - 1)))];
+                tsum[rg] = raw_sum<Elem>(rc, mn);
+            }
+            __builtin_amdgcn_wave_barrier();   // the slot is rewritten by the next pass
+        }
+    }
+}
+
 template <typename Src>
 __device__ __forceinline__ void reduce_w_block_wide(Src w, const WArgs& wa, int64_t b,
                                                     double* lds) {
@@ -1793,13 +1857,33 @@ __device__ __forceinline__ void reduce_w_block_wide(Src w, const WArgs& wa, int6
     const int q = t / kThreads;
     const int row = tr / kRowLanes;
     const int lane = tr % kRowLanes;
-    const int64_t j0 = b * kWBlock + static_cast<int64_t>(q * kRows + row) * kSub + lane * kLane;
-    const int64_t j1 = j0 + static_cast<int64_t>(kSmallRounds) * kRows * kSub;
-    const RawChunk<Elem> r0 = src_raw_n(w, j0, clamp_count(wa.M - j0, kLane));
-    const RawChunk<Elem> r1 = src_raw_n(w, j1, clamp_count(wa.M - j1, kLane));
-    Elem mn = r0.raw(0);
-    const double t0 = raw_sum<Elem>(r0, mn);
-    const double t1 = raw_sum<Elem>(r1, mn);
+    double t0 = 0.0, t1 = 0.0;
+    Elem mn = static_cast<Elem>(0);
+    if constexpr (std::is_pointer<Src>::value && sizeof(Elem) == 8) {
+        // binary64 (a lane chunk is a whole cache line): the wave's chunks of
+        // rounds q and q + 4, 1024 consecutive weights each, of which those
+        // before M exist
+        const int wv = t >> 6;
+        const int64_t o0 = b * kWBlock + static_cast<int64_t>(q) * kRows * kSub +
+                           static_cast<int64_t>(wv % (kThreads / 64)) * 64 * kLane;
+        const int64_t o1 = o0 + static_cast<int64_t>(kSmallRounds) * kRows * kSub;
+        const int n[2] = {clamp_count(wa.M - o0, 64 * kLane), clamp_count(wa.M - o1, 64 * kLane)};
+        double ts[2] = {0.0, 0.0};
+        wide_chunk_sums<Elem>(w + (n[0] > 0 ? o0 : 0), w + (n[1] > 0 ? o1 : 0), n, lds + wv * 256,
+                              ts, mn);
+        t0 = ts[0];
+        t1 = ts[1];
+        lds_barrier();   // the staging slots become the epilogue's
+    } else {
+        // binary32 chunks (two per cache line) and outer products: lane-strided
+        const int64_t j0 = b * kWBlock + static_cast<int64_t>(q * kRows + row) * kSub + lane * kLane;
+        const int64_t j1 = j0 + static_cast<int64_t>(kSmallRounds) * kRows * kSub;
+        const RawChunk<Elem> r0 = src_raw_n(w, j0, clamp_count(wa.M - j0, kLane));
+        const RawChunk<Elem> r1 = src_raw_n(w, j1, clamp_count(wa.M - j1, kLane));
+        mn = r0.raw(0);
+        t0 = raw_sum<Elem>(r0, mn);
+        t1 = raw_sum<Elem>(r1, mn);
+    }
     const int bad = block_any((mn < static_cast<Elem>(0)) ? 1 : 0);
     lane_tot[q * kThreads + tr] = t0;
     lane_tot[(q + kSmallRounds) * kThreads + tr] = t1;
@@ -1841,7 +1925,7 @@ __device__ __forceinline__ void reduce_w_block_wide(Src w, const WArgs& wa, int6
 template <typename T, int P>
 __global__ __launch_bounds__(kSmallThreads) void k_reduce_small(const T* __restrict__ w, WArgs wa,
                                                                ZArgs za) {
-    __shared__ double lds[kWIters * kThreads + 2 * kWSubPerBlock];
+    __shared__ __attribute__((aligned(16))) double lds[kSmallLds];
     if (static_cast<int64_t>(blockIdx.x) < za.nb) {
         reduce_z_block_quads<P>(za, blockIdx.x, lds, lds + kSmallThreads);
         return;
