@@ -1250,7 +1250,7 @@ __device__ __forceinline__ int win_slot(int i) {
 // and the clamp) is monotone in x, so bucket(sw[i]) < bucket(v) implies
 // sw[i] < v, and bucket(sw[i]) > bucket(v) implies sw[i] > v.
 constexpr int kBuckets = 2048;
-constexpr int kPlaceGroup = 4;   // draws whose searches are interleaved
+constexpr int kPlaceGroup = 5;   // draws whose searches are interleaved (groups of 5, 5, 5, 1)
 
 struct WinBuckets {
     double lo;
@@ -1349,17 +1349,23 @@ __device__ __forceinline__ void place_in_window(const double* sw, uint32_t* tbw,
 #pragma unroll
     for (int g = 0; g < kDensePer; g += kPlaceGroup) {
         if (g < nmine) {
-            int a[kPlaceGroup], e[kPlaceGroup];   // the position lies in [a, e]
+            // the position lies in [a, e]; slots past the thread's kDensePer
+            // values (the last group) stay empty, removed once unrolled
+            int a[kPlaceGroup], e[kPlaceGroup];
 #pragma unroll
             for (int k = 0; k < kPlaceGroup; ++k) {
                 const int q = g + k;
-                const bool act = q >= next && q < nmine && (final_window || x[q] <= wend);
-                const int b = bm.of(x[q]);
-                const int ta = tb[b];
-                const int te = tb[b + 1];
-                a[k] = act ? ta : 0;
-                e[k] = act ? te : 0;
-                if (act) nxt = q + 1;
+                a[k] = 0;
+                e[k] = 0;
+                if (q < kDensePer) {
+                    const bool act = q >= next && q < nmine && (final_window || x[q] <= wend);
+                    const int b = bm.of(x[q]);
+                    const int ta = tb[b];
+                    const int te = tb[b + 1];
+                    a[k] = act ? ta : 0;
+                    e[k] = act ? te : 0;
+                    if (act) nxt = q + 1;
+                }
             }
             // a and e stay in 0..nwin-1, so every probe reads inside the window
             for (;;) {
@@ -1368,22 +1374,25 @@ __device__ __forceinline__ void place_in_window(const double* sw, uint32_t* tbw,
 #pragma unroll
                 for (int k = 0; k < kPlaceGroup; ++k) m[k] = (a[k] + e[k]) >> 1;
 #pragma unroll
-                for (int k = 0; k < kPlaceGroup; ++k) sv[k] = sw[win_slot(m[k])];
+                for (int k = 0; k < kPlaceGroup; ++k)
+                    if (g + k < kDensePer) sv[k] = sw[win_slot(m[k])];
                 bool more = false;
 #pragma unroll
                 for (int k = 0; k < kPlaceGroup; ++k) {
-                    const bool go = a[k] < e[k];
-                    const bool below = sv[k] < x[g + k];
-                    a[k] = (go && below) ? m[k] + 1 : a[k];
-                    e[k] = (go && !below) ? m[k] : e[k];
-                    more = more || a[k] < e[k];
+                    if (g + k < kDensePer) {
+                        const bool go = a[k] < e[k];
+                        const bool below = sv[k] < x[g + k];
+                        a[k] = (go && below) ? m[k] + 1 : a[k];
+                        e[k] = (go && !below) ? m[k] : e[k];
+                        more = more || a[k] < e[k];
+                    }
                 }
                 if (!more) break;
             }
 #pragma unroll
             for (int k = 0; k < kPlaceGroup; ++k) {
                 const int q = g + k;
-                if (q >= next && q < nxt) res[q] = static_cast<int32_t>(base + a[k]);
+                if (q < kDensePer && q >= next && q < nxt) res[q] = static_cast<int32_t>(base + a[k]);
             }
         }
     }
