@@ -1058,11 +1058,37 @@ __device__ int64_t locate_subtile_index(const WArgs& wa, const double* sbeta, in
     return b * kWSubPerBlock + quad_sum(cnt);
 }
 
-template <typename Src>
+// locate_subtile's result from locate_subtile_index and four loads of the
+// sub-tile's bases: the same search and predicate with few registers.
+__device__ SubtileLoc locate_subtile_lean(const WArgs& wa, const double* sbeta, int64_t kstride,
+                                          int ns, double x, int qi) {
+    const int64_t g = locate_subtile_index(wa, sbeta, kstride, ns, x, qi);
+    SubtileLoc L;
+    L.b = g / kWSubPerBlock;
+    L.s = static_cast<int>(g % kWSubPerBlock);
+    L.beta_b = (L.b == 0) ? 0.0 : wa.beta[L.b - 1];
+    L.beta_n = wa.beta[L.b];
+    L.blk0 = L.b * kWBlock;
+    const int64_t blen = (wa.M - L.blk0 < kWBlock) ? wa.M - L.blk0 : kWBlock;
+    L.jlast = L.blk0 + blen - 1;
+    L.nsub = static_cast<int>((blen + kSub - 1) / kSub);
+    L.X = wa.sub_end[L.b * kWSubPerBlock + kWSubPerBlock - 1];
+    L.sigma = (L.s == 0) ? 0.0 : wa.sub_end[L.b * kWSubPerBlock + L.s - 1];
+    return L;
+}
+
+// kLean: for a caller at its register limit (the dense map's wide chunks):
+// the lean sub-tile location, and chunk totals summed one chunk at a time, the
+// chosen chunk loaded again for the element level.  Same sums, same index.
+template <typename Src, bool kLean = false>
 __device__ void map_quad(Src w, const WArgs& wa, const double* sbeta, int64_t kstride, int ns,
                          double x, int64_t i, int qi, int32_t* __restrict__ r, int vec_ok) {
     using Elem = typename SrcElem<Src>::type;
-    const SubtileLoc loc = locate_subtile(wa, sbeta, kstride, ns, x, qi);
+    SubtileLoc loc;
+    if constexpr (kLean)
+        loc = locate_subtile_lean(wa, sbeta, kstride, ns, x, qi);
+    else
+        loc = locate_subtile(wa, sbeta, kstride, ns, x, qi);
     const int64_t blk0 = loc.blk0, jlast = loc.jlast;
     const int s = loc.s;
     const double beta_b = loc.beta_b, beta_n = loc.beta_n, sigma = loc.sigma, X = loc.X;
@@ -1076,9 +1102,21 @@ __device__ void map_quad(Src w, const WArgs& wa, const double* sbeta, int64_t ks
     constexpr int kChunks = kRowLanes / kQuad;
     static_assert(kQuad == 4 && kChunks == 4, "four lanes per quad, four chunks per lane");
     double tl[kChunks];   // tl[q] = total of chunk qi + 4q
-    const bool full_sub = (slen == kSub) && (vec_ok & 1);
+    const bool full_sub = !kLean && (slen == kSub) && (vec_ok & 1);
     RawChunk<Elem> rc[kChunks];
-    if (full_sub) {
+    if constexpr (kLean) {
+#pragma unroll 1
+        for (int q = 0; q < kChunks; ++q) {
+            const int l = qi + kQuad * q;
+            const int nv = (l < nl) ? ((slen - l * kLane < kLane) ? slen - l * kLane : kLane) : 0;
+            double xx[kLane];
+            src_chunk(w, sub0 + l * kLane, nv, (vec_ok & 1) != 0, xx);
+            const double ts = chunk_sum(xx);
+#pragma unroll
+            for (int qq = 0; qq < kChunks; ++qq)
+                if (qq == q) tl[qq] = ts;
+        }
+    } else if (full_sub) {
 #pragma unroll
         for (int q = 0; q < kChunks; ++q)
             rc[q] = src_raw(w, sub0 + (qi + kQuad * q) * kLane);
@@ -1484,7 +1522,7 @@ __device__ __forceinline__ void map_wide_chunk(Src w, const WArgs& wa, const ZAr
     lds_barrier();
     for (int64_t i = c0 + t / kQuad; i < c1; i += kUPerWG) {
         const double x = threshold_for(uniform_at(za, ztot, i), total);
-        map_quad<Src>(w, wa, sbeta, kstride, ns, x, i, t & (kQuad - 1), r, vec_ok);
+        map_quad<Src, true>(w, wa, sbeta, kstride, ns, x, i, t & (kQuad - 1), r, vec_ok);
     }
 }
 
