@@ -1276,9 +1276,12 @@ static_assert(kWinLen <= kBetaLds, "the window reuses the block-end stage");
 // LDS slot of window entry i: within each group of 16 entries (the 16 a
 // thread writes when it fills the window) the slots are rotated by the group's
 // index, so that the 64 lanes of a wave writing their k-th entries spread over
-// the banks instead of meeting in one.
+// the banks instead of meeting in one.  Unsigned arithmetic (i >= 0): the
+// searches compute this for every probe, and a signed quotient costs three
+// more instructions each time.
 __device__ __forceinline__ int win_slot(int i) {
-    return (i & ~(kLane - 1)) | ((i & (kLane - 1)) ^ ((i / kLane) & (kLane - 1)));
+    const unsigned u = static_cast<unsigned>(i);
+    return static_cast<int>(u ^ ((u / kLane) & (kLane - 1)));
 }
 
 // Bucket index of a window of non-decreasing values: with lo the first value
