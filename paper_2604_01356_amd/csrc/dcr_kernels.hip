@@ -2643,15 +2643,16 @@ __device__ void map_seg_chunk(const Tin* __restrict__ w, const WArgs& wa, const 
                 const int pos = pb + t + m * kThreads;
                 const bool v = pos < d1;
                 const int k = v ? L.srank[pos] : p0;
-                const int32_t g = L.lsub[k];
+                // sub-tile ids are not negative: unsigned quotients are shifts
+                const uint32_t g = static_cast<uint32_t>(L.lsub[k]);
                 const int64_t b = g / kWSubPerBlock;
-                const int s = g % kWSubPerBlock;
+                const int s = static_cast<int>(g % kWSubPerBlock);
                 xx[m] = v ? L.sx[pos] : -__builtin_huge_val();
                 const int64_t blk0 = b * kWBlock;
                 const int64_t jlast = ((blk0 + kWBlock < wa.M) ? blk0 + kWBlock : wa.M) - 1;
                 const int64_t sub0 = blk0 + static_cast<int64_t>(s) * kSub;
                 const int slen = static_cast<int>((jlast - sub0 + 1 < kSub) ? jlast - sub0 + 1 : kSub);
-                nl[m] = (slen + kLane - 1) / kLane;
+                nl[m] = static_cast<int>(static_cast<unsigned>(slen + kLane - 1) / kLane);
                 bb[m] = (b == 0) ? 0.0 : beta_end(b - 1);
                 bn[m] = beta_end(b);
                 sg[m] = sigma_of(b, s);
